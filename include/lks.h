@@ -1,0 +1,194 @@
+/*
+ * lks.h -- C ABI of liblks.so: the fused kinetic update with local kinetic
+ * refinement sensors on AMD Instinct MI355X (gfx950).
+ *
+ * Method ("Local kinetic sensors for adaptive mesh and algorithm refinement",
+ * arXiv 2603.13618):
+ *   - populations f_i on a tensor-product Gauss-Hermite velocity set
+ *     (Sec. II.A.3): D2Q9 (GH3 x GH3, velocities in {-1,0,1}^2, T_ref = 1/3,
+ *     isothermal, order-2 Grad-Hermite equilibrium) or D2Q25 (GH5 x GH5,
+ *     T_ref = 1, order-4 Grad-Hermite equilibrium);
+ *   - D2Q9: one lattice-BGK step = pull streaming g_i(x) = f_i(x - c_i) on a
+ *     periodic grid, then f_i' = g_i - (g_i - f^eq_i)/tau (the collision of
+ *     Sec. II.A.1 with tau1 = tau2);
+ *   - D2Q25: one explicit-Euler finite-volume step (eq. finalDiscretePDE)
+ *     with van Leer limited upwind fluxes and BGK relaxation, tau = mu/(rho T);
+ *   - in the same pass, on the pre-collision populations of the step, the
+ *     sensors S_KL (eq. HKL-sensor), S_NEQ (eq. sensor-neq-kin), S_PI
+ *     (eq. sensor-TauNS-kin) and, on D2Q25, S_Q (eq. sensor-qNSF-kin-ryk,
+ *     g = 0), and the per-cell refinement flag (Sec. II.B.2, regridding step 1).
+ *
+ * Conventions
+ *   Layout: structure of arrays, plane-major [k][ny][nx], x fastest.
+ *     Population index i = q1*a + b, a = x-node, b = y-node index (ascending),
+ *     q1 = 3 or 5.  D2Q9 velocity i is (a-1, b-1).
+ *   Storage: populations are stored as deviations d_i = f_i - w_i*rho0 in the
+ *     configured dtype (F64, F32, BF16, F16; 16-bit formats rounded to nearest
+ *     even); all arithmetic is FP32 (FP64 for F64 storage); global sums are
+ *     FP64.
+ *   Sensors: plane s = 0 S_KL, 1 S_NEQ, 2 S_PI, 3 S_Q (D2Q25 only), so D2Q9
+ *     has 3 planes and D2Q25 4.  float, or double for F64 storage.
+ *   Flags: uint8 per cell; bits 0-1 = refinement level = max over the sensors
+ *     in flag_mask of [s > thr[s][0]] + [s > thr[s][1]]; bit 7 = positivity
+ *     fault (some f_i or f^eq_i not > 0, or NaN: S_KL = +inf, level 2).
+ *   Sums: per step LKS_NSUMS doubles: total mass, x- and y-momentum, total
+ *     energy (0 on D2Q9), then the totals of S_KL, S_NEQ, S_PI, S_Q over all
+ *     cells, all of the pre-collision state.  Step k (counted from 1 since
+ *     init) writes row (k-1) mod max_steps.
+ *
+ * Ownership: the caller allocates and frees ALL device memory (buffers must
+ *   outlive their use by the context); the context holds pointers, parameters
+ *   and a few bytes of host state.  lks_destroy frees only the context.
+ * Streams: every call that launches work enqueues it on the stream given at
+ *   creation and returns without waiting; device errors surface at the next
+ *   call that synchronises (lks_read_host, lks_check).  One context serves one
+ *   stream and one host thread at a time.
+ * Errors: every call returns an lks_status and throws nothing.  Invalid
+ *   arguments return LKS_EINVAL before anything is launched; lks_last_error
+ *   gives the message.
+ */
+#ifndef LKS_H
+#define LKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LKS_NSUMS 8
+#define LKS_MAX_SENSORS 4
+
+typedef struct lks_ctx lks_ctx;
+
+typedef enum {
+    LKS_OK = 0,
+    LKS_EINVAL = 1,       /* invalid argument or configuration              */
+    LKS_ESTATE = 2,       /* call out of order (e.g. step before init)      */
+    LKS_EHIP = 3,         /* HIP runtime error (message in lks_last_error)  */
+    LKS_ENONPOS = 4,      /* lks_check: positivity faults were counted      */
+    LKS_ENAN = 5,         /* lks_check: a global sum is NaN                 */
+    LKS_EUNSUPPORTED = 6  /* valid but not implemented combination          */
+} lks_status;
+
+enum { LKS_D2Q9 = 9, LKS_D2Q25 = 25 };
+enum { LKS_F64 = 0, LKS_F32 = 1, LKS_BF16 = 2, LKS_F16 = 3 };
+enum { LKS_PERIODIC = 0, LKS_OUTFLOW = 1 };
+enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u };
+
+typedef struct {
+    int32_t lattice;      /* LKS_D2Q9 or LKS_D2Q25                              */
+    int32_t nx, ny;       /* grid size, >= 1 each (D2Q9 and periodic D2Q25
+                             axes need no minimum; see lks_create)             */
+    int32_t dtype;        /* population storage, LKS_F64..LKS_F16               */
+    int32_t bc_x, bc_y;   /* D2Q25: LKS_PERIODIC or LKS_OUTFLOW (zero-gradient,
+                             two ghost layers); D2Q9: must be LKS_PERIODIC     */
+    double tau;           /* D2Q9 relaxation time in steps, > 0.5              */
+    double mu, dt, dx;    /* D2Q25: dynamic viscosity, time step, cell size
+                             (tau = mu/(rho T) per cell, R = 1); all > 0       */
+    double rho0;          /* deviation reference density, > 0 (normally 1)     */
+    uint32_t flag_mask;   /* sensors that drive the flags, LKS_S_* bits        */
+    int32_t launch_rows;  /* rows per workgroup of the cell kernels; 0 picks
+                             automatically (a launch-shape hint only)          */
+    double thr[LKS_MAX_SENSORS][2]; /* (theta1 <= theta2) per sensor; compared
+                             in the compute precision; +INF disables           */
+    int32_t max_steps;    /* rows of the sums buffer, >= 1                     */
+    int32_t launch_vec;   /* cells per thread along x of the cell kernels (1, 2
+                             or 4); 0 picks the widest the row length and the
+                             buffer alignment allow (a launch-shape hint only) */
+} lks_config;
+
+typedef struct {
+    void* pop[2];         /* [Q][ny][nx] dtype, ping-pong state buffers        */
+    void* sensors;        /* [nsens][ny][nx] float (double for F64)            */
+    uint8_t* flags;       /* [ny][nx]                                          */
+    double* sums;         /* [max_steps][LKS_NSUMS]                            */
+    void* scratch;        /* >= lks_scratch_bytes(cfg) bytes, 256-B aligned    */
+    size_t scratch_bytes;
+} lks_buffers;
+
+/* Device bytes of scratch the configuration needs (per-block FP64 partial
+ * sums and counters).  0 for an invalid configuration. */
+size_t lks_scratch_bytes(const lks_config* cfg);
+
+/* Number of sensor planes of a lattice (3 for D2Q9, 4 for D2Q25), 0 if invalid. */
+int32_t lks_num_sensors(int32_t lattice);
+
+/* Validate cfg and buffers and create a context bound to hip_stream (a
+ * hipStream_t; NULL = the null stream).  No kernel is launched. */
+lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_stream,
+                      lks_ctx** out);
+
+/* Fill pop[0] with the equilibrium of the given FP64 device fields [ny][nx]
+ * (the equilibrium initial condition of Sec. IV); T may be NULL on D2Q9
+ * (isothermal) and is required on D2Q25.  Resets the step count to 0. */
+lks_status lks_init_equilibrium(lks_ctx* ctx, const double* rho, const double* ux,
+                                const double* uy, const double* T);
+
+/* Declare that pop[pop_index] already holds a state (e.g. a copied-in
+ * checkpoint) reached after steps_done steps. */
+lks_status lks_restore(lks_ctx* ctx, int32_t pop_index, int64_t steps_done);
+
+/* Advance nsteps (>= 0) steps.  fused = 1: one fused kernel per step (stream
+ * or flux + collide + sensors + flags + sums).  fused = 0: the same result
+ * from separate passes (D2Q9 only: stream into the other buffer, sensors and
+ * flags, collide back), kept as the unfused baseline.  After the call
+ * sensors and flags hold the last step's values. */
+lks_status lks_step(lks_ctx* ctx, int32_t nsteps, int32_t fused);
+
+/* One fused step from the state src into dst (both [Q][ny][nx] in the
+ * context's dtype, distinct, neither need be pop[0]/pop[1]); sensors and
+ * flags receive this step's values, the sums buffer and the step count are
+ * left unchanged.  Used to recompute trajectory segments from checkpoints. */
+lks_status lks_step_from(lks_ctx* ctx, const void* src, void* dst);
+
+/* Index of the buffer holding the current state and the step count. */
+lks_status lks_current(const lks_ctx* ctx, int32_t* pop_index, int64_t* steps_done);
+
+/* Moments of the current state into FP64 device arrays [ny][nx]: rho, ux,
+ * uy and, when T != NULL, the temperature (T_ref = 1/3 on D2Q9). */
+lks_status lks_moments(lks_ctx* ctx, double* rho, double* ux, double* uy, double* T);
+
+/* Synchronise the stream and copy to host memory: what = 0 current
+ * populations, 1 sensors, 2 flags, 3 sums.  bytes must equal the buffer size. */
+lks_status lks_read_host(lks_ctx* ctx, int32_t what, void* host_dst, size_t bytes);
+
+/* Synchronise; report the number of positivity-fault cells counted since
+ * init (LKS_ENONPOS if > 0) and LKS_ENAN if a stored sum of mass or momentum
+ * is NaN. */
+lks_status lks_check(lks_ctx* ctx, int64_t* n_nonpos);
+
+/* ---- Adjoint of the D2Q9 step (gradient of the summed smooth KL sensor) ----
+ * Loss L = sum_x S_KL(g_N(x)), g_N the pre-collision populations of the last
+ * step N, initial populations at the equilibrium of (rho0, u0).  All arrays
+ * are device [9][ny][nx] in the context's dtype (F32 or F64) unless stated.
+ *   seed:  lam_out = dL/dg_N, from pop_prev = f_{N-1} (the state before step N)
+ *   step:  lam_out = dL/dg_n = J_C(g_n)^T S^T lam_in, lam_in = dL/dg_{n+1},
+ *          pop_prev = f_{n-1}; J_C is the BGK collision Jacobian and S^T the
+ *          adjoint of pull streaming (a pull by +c_i)
+ *   init:  dL/du0 from lam0 = dL/dg_1 and the FP64 initial fields [ny][nx];
+ *          writes FP64 gux, guy [ny][nx]. */
+lks_status lks_adjoint_seed_kl(lks_ctx* ctx, const void* pop_prev, void* lam_out);
+lks_status lks_adjoint_step(lks_ctx* ctx, const void* pop_prev, const void* lam_in,
+                            void* lam_out);
+lks_status lks_adjoint_init(lks_ctx* ctx, const double* rho0, const double* ux0,
+                            const double* uy0, const void* lam0, double* gux, double* guy);
+
+lks_status lks_destroy(lks_ctx* ctx);
+
+const char* lks_status_str(lks_status s);
+
+/* Message of the last failed call on ctx (or of the last failed lks_create
+ * when ctx is NULL); valid until the next call on the same context. */
+const char* lks_last_error(const lks_ctx* ctx);
+
+/* Plain device-to-device copy of bytes (multiple of 16, 16-B aligned
+ * pointers) on hip_stream: the bandwidth yardstick used to calibrate traffic
+ * counters and the attainable HBM rate. */
+lks_status lks_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LKS_H */

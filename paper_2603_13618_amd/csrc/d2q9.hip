@@ -1,0 +1,370 @@
+// d2q9.hip -- D2Q9 lattice-BGK kernels for gfx950: the fused
+// stream + collide + sensors + flags + FP64 sums pass, the three passes of the
+// unfused baseline, the equilibrium initialiser and the moment readout.
+//
+// Method (arXiv 2603.13618): D2Q9 = GH3 x GH3 velocity set, order-2
+// Grad-Hermite equilibrium (Sec. II.A.3), single-relaxation BGK (the QE
+// collision of Sec. II.A.1 with tau1 = tau2), sensors S_KL (eq. HKL-sensor),
+// S_NEQ (eq. sensor-neq-kin) and S_PI (eq. sensor-TauNS-kin) on the
+// pre-collision populations, refinement flags (Sec. II.B.2, step 1).
+//
+// Memory layout: SoA planes [9][ny][nx] of deviations d_i = f_i - w_i rho0.
+// One thread owns VEC consecutive cells of a row, so every population plane is
+// read with one aligned VEC-wide load per thread; the x-shifted populations
+// take their one missing neighbour from the adjacent lane (ds_bpermute) and
+// only the wave's edge lanes touch memory for it.  Pull streaming reads each
+// stored value exactly once, so HBM traffic is one read and one write per
+// population plus the sensor planes and the flag byte.
+#include "lks_device.h"
+#include "lks_internal.h"
+
+namespace lks {
+
+// velocity i = 3a + b: c = (a - 1, b - 1); weights (1/6, 2/3, 1/6)^2
+__device__ __forceinline__ constexpr int cx9(int i) { return i / 3 - 1; }
+__device__ __forceinline__ constexpr int cy9(int i) { return i % 3 - 1; }
+template <typename R>
+__device__ __forceinline__ constexpr R w9(int i)
+{
+    return (i == 4) ? R(4.0 / 9.0) : ((cx9(i) == 0 || cy9(i) == 0) ? R(1.0 / 9.0) : R(1.0 / 36.0));
+}
+
+template <int N, typename F, int I = 0>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, F, I + 1>(static_cast<F&&>(f));
+    }
+}
+
+// Load VEC cells of row `row` starting at x0, shifted by cx along x
+// (periodic): out[k] = row[(x0 + k - CX) mod nx].
+template <int CX, typename S, int VEC>
+__device__ __forceinline__ void pull_row(const typename Store<S>::raw* __restrict__ row, int x0,
+                                         int nx, bool active, int lane,
+                                         typename Store<S>::real (&out)[VEC])
+{
+    using R = typename Store<S>::real;
+    R a[VEC];
+    if (active) {
+        load_vec<S, VEC>(row + x0, a);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) a[k] = R(0);
+    }
+    if constexpr (CX == 0) {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) out[k] = a[k];
+    } else if constexpr (CX == 1) {
+        R prev = __shfl_up(a[VEC - 1], 1, kWave);
+        if (active && (lane == 0 || x0 == 0))
+            prev = Store<S>::to_real(row[x0 == 0 ? nx - 1 : x0 - 1]);
+        out[0] = prev;
+#pragma unroll
+        for (int k = 1; k < VEC; ++k) out[k] = a[k - 1];
+    } else {
+        R next = __shfl_down(a[0], 1, kWave);
+        if (active && (lane == kWave - 1 || x0 + VEC >= nx))
+            next = Store<S>::to_real(row[x0 + VEC >= nx ? 0 : x0 + VEC]);
+#pragma unroll
+        for (int k = 0; k + 1 < VEC; ++k) out[k] = a[k + 1];
+        out[VEC - 1] = next;
+    }
+}
+
+template <typename S, int VEC, int PASS>
+__global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
+    D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
+    typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags,
+    double* __restrict__ partials, unsigned long long* __restrict__ faults)
+{
+    using R = typename Store<S>::real;
+    using raw = typename Store<S>::raw;
+    constexpr bool PULL = (PASS == kFused || PASS == kStream);
+    constexpr bool SENSE = (PASS == kFused || PASS == kSense);
+    constexpr bool COLLIDE = (PASS == kFused || PASS == kCollide);
+
+    const int nx = a.nx, ny = a.ny;
+    const long long plane = a.plane;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int tx = blockIdx.x % a.g.tiles_x;
+    const int rg = blockIdx.x / a.g.tiles_x;
+    const int x0 = (tx * kBlock + threadIdx.x) * VEC;
+    const bool active = x0 < nx;
+
+    const R rho0 = R(a.rho0);
+    const R inv_tau = R(1.0 / a.tau);
+    R th[3][2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        th[s][0] = R(a.thr[s][0]);
+        th[s][1] = R(a.thr[s][1]);
+    }
+    double acc[kNsums];
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
+    unsigned nfault = 0;
+
+    for (int r = 0; r < a.g.rows; ++r) {
+        const int y = rg * a.g.rows + r;
+        if (y >= ny) break;                       // uniform across the workgroup
+        R d[9][VEC];                              // d[i][cell]
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int cx = PULL ? cx9(i) : 0;
+            constexpr int cy = PULL ? cy9(i) : 0;
+            int ys = y - cy;
+            ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+            R v[VEC];
+            pull_row<cx, S, VEC>(fin + i * plane + (long long)ys * nx, x0, nx, active, lane, v);
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) d[i][k] = v[k];
+        });
+        const long long off = (long long)y * nx + x0;
+
+        if constexpr (PASS == kStream) {
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, d[i]);
+            }
+            continue;
+        } else {
+            R s_kl[VEC], s_neq[VEC], s_pi[VEC];
+            uint8_t fl[VEC];
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                // moments of the pre-collision populations (deviation form)
+                R drho = R(0), jx = R(0), jy = R(0);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    drho += d[i][k];
+                    if (cx9(i) != 0) jx += R(cx9(i)) * d[i][k];
+                    if (cy9(i) != 0) jy += R(cy9(i)) * d[i][k];
+                }
+                const R rho = rho0 + drho;
+                const R irho = rcp(rho);
+                const R ux = jx * irho, uy = jy * irho;
+                const R usq15 = R(1.5) * (ux * ux + uy * uy);
+                // equilibrium deviations
+                // f^eq_i - w_i rho0 = w_i [(rho - rho0) + rho (3cu + 9/2 cu^2 - 3/2 u^2)]
+                R deq[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const R cu = R(cx9(i)) * ux + R(cy9(i)) * uy;
+                    const R P = cu * (R(3) + R(4.5) * cu) - usq15;
+                    deq[i] = w9<R>(i) * (drho + rho * P);
+                }
+                // The rounded weights make sum_i c_i f^eq_i differ from rho u by a
+                // relative ~1e-8 in FP32, a bias that the collision would feed back
+                // every step.  Close the x- and y-momentum on the axis pairs and the
+                // mass on the rest population (exact-arithmetic no-ops).
+                {
+                    const R rx = jx - ((deq[6] + deq[7] + deq[8]) - (deq[0] + deq[1] + deq[2]));
+                    const R ry = jy - ((deq[2] + deq[5] + deq[8]) - (deq[0] + deq[3] + deq[6]));
+                    deq[7] += R(0.5) * rx;
+                    deq[1] -= R(0.5) * rx;
+                    deq[5] += R(0.5) * ry;
+                    deq[3] -= R(0.5) * ry;
+                    R rest = R(0);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        if (i != 4) rest += deq[i];
+                    deq[4] = drho - rest;
+                }
+                R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
+                bool fault = false;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int cx = cx9(i), cy = cy9(i);
+                    const R fneq = d[i][k] - deq[i];
+                    if constexpr (SENSE) {
+                        const R feq = w9<R>(i) * rho0 + deq[i];
+                        const R f = w9<R>(i) * rho0 + d[i][k];
+                        fault |= !(f > R(0)) || !(feq > R(0));
+                        kl += feq * kl_phi(fneq * rcp(feq));
+                        neq += fabs(fneq);
+                        if (cx != 0) pxx += fneq;
+                        if (cy != 0) pyy += fneq;
+                        if (cx * cy != 0) pxy += R(cx * cy) * fneq;
+                    }
+                    if constexpr (COLLIDE) d[i][k] -= inv_tau * fneq;
+                }
+                if constexpr (SENSE) {
+                    const R spi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+                    if (fault) kl = R(INFINITY);
+                    int level = 0;
+                    const R sv[3] = {kl, neq, spi};
+#pragma unroll
+                    for (int s = 0; s < 3; ++s) {
+                        if (a.mask & (1u << s)) {
+                            const int l = (sv[s] > th[s][0]) + (sv[s] > th[s][1]);
+                            level = l > level ? l : level;
+                        }
+                    }
+                    fl[k] = fault ? uint8_t(0x82) : uint8_t(level);
+                    s_kl[k] = kl;
+                    s_neq[k] = neq;
+                    s_pi[k] = spi;
+                    if (active) {
+                        acc[0] += (double)drho;
+                        acc[1] += (double)jx;
+                        acc[2] += (double)jy;
+                        acc[4] += (double)kl;
+                        acc[5] += (double)neq;
+                        acc[6] += (double)spi;
+                        nfault += fault ? 1u : 0u;
+                    }
+                }
+            }
+            if (active) {
+                if constexpr (COLLIDE) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, d[i]);
+                }
+                if constexpr (SENSE) {
+                    store_pack<R, VEC>(sens + off, s_kl);
+                    store_pack<R, VEC>(sens + plane + off, s_neq);
+                    store_pack<R, VEC>(sens + 2 * plane + off, s_pi);
+                    store_pack<uint8_t, VEC>(flags + off, fl);
+                }
+            }
+        }
+    }
+    if constexpr (SENSE) {
+        if (nfault) atomicAdd(faults, (unsigned long long)nfault);
+        block_sums(acc, partials + (long long)blockIdx.x * kNsums);
+    }
+}
+
+template <typename S, int VEC>
+static hipError_t launch_pass(int pass, const D2Q9Args& a, const void* fin, void* fout, void* sens,
+                              uint8_t* flags, double* partials, unsigned long long* faults,
+                              hipStream_t st)
+{
+    using raw = typename Store<S>::raw;
+    using R = typename Store<S>::real;
+    const raw* in = static_cast<const raw*>(fin);
+    raw* out = static_cast<raw*>(fout);
+    R* sv = static_cast<R*>(sens);
+    const dim3 grid(a.g.nblocks), block(kBlock);
+    switch (pass) {
+    case kFused:
+        d2q9_kernel<S, VEC, kFused><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        break;
+    case kStream:
+        d2q9_kernel<S, VEC, kStream><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        break;
+    case kSense:
+        d2q9_kernel<S, VEC, kSense><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        break;
+    case kCollide:
+        d2q9_kernel<S, VEC, kCollide><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename S, int VWIDE>
+static hipError_t launch_vec(int pass, const D2Q9Args& a, const void* fin, void* fout, void* sens,
+                             uint8_t* flags, double* partials, unsigned long long* faults,
+                             hipStream_t st)
+{
+    switch (a.g.vec) {
+    case 1: return launch_pass<S, 1>(pass, a, fin, fout, sens, flags, partials, faults, st);
+    case 2: return launch_pass<S, 2>(pass, a, fin, fout, sens, flags, partials, faults, st);
+    case 4:
+        if constexpr (VWIDE >= 4) return launch_pass<S, 4>(pass, a, fin, fout, sens, flags, partials, faults, st);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_d2q9(int dtype, int pass, const D2Q9Args& a, const void* fin, void* fout,
+                       void* sens, uint8_t* flags, double* partials, unsigned long long* faults,
+                       hipStream_t s)
+{
+    switch (dtype) {
+    case 0: return launch_vec<double, 2>(pass, a, fin, fout, sens, flags, partials, faults, s);
+    case 1: return launch_vec<float, 4>(pass, a, fin, fout, sens, flags, partials, faults, s);
+    case 2: return launch_vec<bf16_t, 4>(pass, a, fin, fout, sens, flags, partials, faults, s);
+    case 3: return launch_vec<f16_t, 4>(pass, a, fin, fout, sens, flags, partials, faults, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium initialiser and moment readout (one thread per cell, FP64 math)
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(kBlock) void d2q9_init_kernel(long long n, double rho0, const double* __restrict__ rho,
+                                                      const double* __restrict__ ux,
+                                                      const double* __restrict__ uy,
+                                                      typename Store<S>::raw* __restrict__ pop)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    const double r = rho[c], u = ux[c], v = uy[c];
+    const double usq15 = 1.5 * (u * u + v * v);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double cu = cx9(i) * u + cy9(i) * v;
+        const double deq = w9<double>(i) * ((r - rho0) + r * (cu * (3.0 + 4.5 * cu) - usq15));
+        pop[i * n + c] = Store<S>::from_real((typename Store<S>::real)deq);
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void d2q9_moments_kernel(long long n, double rho0,
+                                                         const typename Store<S>::raw* __restrict__ pop,
+                                                         double* __restrict__ rho, double* __restrict__ ux,
+                                                         double* __restrict__ uy, double* __restrict__ T)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    double drho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double d = (double)Store<S>::to_real(pop[i * n + c]);
+        drho += d;
+        jx += cx9(i) * d;
+        jy += cy9(i) * d;
+    }
+    const double r = rho0 + drho;
+    rho[c] = r;
+    ux[c] = jx / r;
+    uy[c] = jy / r;
+    if (T) T[c] = 1.0 / 3.0;
+}
+
+hipError_t launch_d2q9_init(int dtype, long long n, double rho0, const double* rho, const double* ux,
+                            const double* uy, void* pop, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    switch (dtype) {
+    case 0: d2q9_init_kernel<double><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (double*)pop); break;
+    case 1: d2q9_init_kernel<float><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (float*)pop); break;
+    case 2: d2q9_init_kernel<bf16_t><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (uint16_t*)pop); break;
+    case 3: d2q9_init_kernel<f16_t><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (uint16_t*)pop); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_d2q9_moments(int dtype, long long n, double rho0, const void* pop, double* rho,
+                               double* ux, double* uy, double* T, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    switch (dtype) {
+    case 0: d2q9_moments_kernel<double><<<grid, block, 0, s>>>(n, rho0, (const double*)pop, rho, ux, uy, T); break;
+    case 1: d2q9_moments_kernel<float><<<grid, block, 0, s>>>(n, rho0, (const float*)pop, rho, ux, uy, T); break;
+    case 2: d2q9_moments_kernel<bf16_t><<<grid, block, 0, s>>>(n, rho0, (const uint16_t*)pop, rho, ux, uy, T); break;
+    case 3: d2q9_moments_kernel<f16_t><<<grid, block, 0, s>>>(n, rho0, (const uint16_t*)pop, rho, ux, uy, T); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+} // namespace lks

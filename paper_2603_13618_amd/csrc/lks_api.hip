@@ -1,0 +1,408 @@
+// lks_api.hip -- the extern "C" surface of liblks.so (declared in
+// include/lks.h): validation, launch shapes, ping-pong bookkeeping, stream
+// handling and error reporting.  All device memory belongs to the caller.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lks.h"
+#include "lks_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxChunk = 64;          // steps whose partial sums are reduced together
+constexpr size_t kHeader = 256;        // scratch: fault counter, padded
+
+thread_local std::string g_create_err;
+
+int q_of(int lattice) { return lattice == LKS_D2Q9 ? 9 : (lattice == LKS_D2Q25 ? 25 : 0); }
+int nsens_of(int lattice) { return lattice == LKS_D2Q9 ? 3 : (lattice == LKS_D2Q25 ? 4 : 0); }
+size_t store_bytes(int dtype) { return dtype == LKS_F64 ? 8 : (dtype == LKS_F32 ? 4 : 2); }
+size_t sens_bytes(int dtype) { return dtype == LKS_F64 ? 8 : 4; }
+int wide_vec(int dtype) { return dtype == LKS_F64 ? 2 : 4; }
+
+// Launch shape of the D2Q9 cell kernels for a given vector width.
+lks::GridShape d2q9_shape(const lks_config& c, int vec)
+{
+    lks::GridShape g;
+    g.vec = vec;
+    g.tiles_x = (c.nx + kBlock * vec - 1) / (kBlock * vec);
+    int rows = c.launch_rows;
+    if (rows <= 0) {
+        // aim at ~4096 workgroups (16 per CU) so partial sums stay small
+        const long long target = 4096;
+        long long r = ((long long)g.tiles_x * c.ny) / target;
+        rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
+    }
+    if (rows > c.ny) rows = c.ny;
+    g.rows = rows;
+    const long long groups = (long long)((c.ny + rows - 1) / rows) * g.tiles_x;
+    g.nblocks = (int)groups;
+    return g;
+}
+
+const char* validate_config(const lks_config* c)
+{
+    if (!c) return "config is NULL";
+    if (c->lattice != LKS_D2Q9 && c->lattice != LKS_D2Q25) return "lattice must be 9 or 25";
+    if (c->nx < 1 || c->ny < 1) return "nx and ny must be >= 1";
+    if ((long long)c->nx * c->ny > (1LL << 36)) return "grid too large";
+    if (c->dtype < LKS_F64 || c->dtype > LKS_F16) return "dtype must be F64, F32, BF16 or F16";
+    if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0)) return "rho0 must be finite and > 0";
+    if (c->max_steps < 1) return "max_steps must be >= 1";
+    if (c->launch_rows < 0) return "launch_rows must be >= 0";
+    if (c->launch_vec != 0 && c->launch_vec != 1 && c->launch_vec != 2 && c->launch_vec != 4)
+        return "launch_vec must be 0, 1, 2 or 4";
+    if (c->dtype == LKS_F64 && c->launch_vec == 4) return "launch_vec 4 is not available for F64";
+    const unsigned valid = c->lattice == LKS_D2Q9 ? 7u : 15u;
+    if (c->flag_mask & ~valid) return "flag_mask names a sensor this lattice does not have";
+    for (int s = 0; s < LKS_MAX_SENSORS; ++s) {
+        if (std::isnan(c->thr[s][0]) || std::isnan(c->thr[s][1])) return "threshold is NaN";
+        if (c->thr[s][0] > c->thr[s][1]) return "thresholds must satisfy theta1 <= theta2";
+    }
+    if (c->lattice == LKS_D2Q9) {
+        if (c->bc_x != LKS_PERIODIC || c->bc_y != LKS_PERIODIC) return "D2Q9 grids are periodic";
+        if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return "tau must be finite and > 0.5";
+    } else {
+        if ((c->bc_x != LKS_PERIODIC && c->bc_x != LKS_OUTFLOW) ||
+            (c->bc_y != LKS_PERIODIC && c->bc_y != LKS_OUTFLOW))
+            return "bc must be PERIODIC or OUTFLOW";
+        if (!(c->mu > 0.0) || !(c->dt > 0.0) || !(c->dx > 0.0) || !std::isfinite(c->mu) ||
+            !std::isfinite(c->dt) || !std::isfinite(c->dx))
+            return "mu, dt and dx must be finite and > 0";
+    }
+    return nullptr;
+}
+
+size_t scratch_for(const lks_config& c)
+{
+    // sized for the narrowest vector width, which has the most workgroups
+    const lks::GridShape g = d2q9_shape(c, 1);
+    const int chunk = c.max_steps < kMaxChunk ? c.max_steps : kMaxChunk;
+    return kHeader + (size_t)chunk * (size_t)g.nblocks * lks::kNsumsHost * sizeof(double);
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+} // namespace
+
+struct lks_ctx {
+    lks_config cfg;
+    lks_buffers buf;
+    hipStream_t stream;
+    int Q, nsens;
+    long long n;
+    int cur;
+    int64_t steps;
+    bool ready;
+    int chunk;
+    lks::D2Q9Args a9;
+    double* partials;
+    unsigned long long* faults;
+    std::string err;
+};
+
+namespace {
+
+lks_status fail(lks_ctx* c, lks_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return s;
+}
+
+lks_status hip_check(lks_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return LKS_OK;
+    return fail(c, LKS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+} // namespace
+
+extern "C" {
+
+size_t lks_scratch_bytes(const lks_config* cfg)
+{
+    if (validate_config(cfg)) return 0;
+    return scratch_for(*cfg);
+}
+
+int32_t lks_num_sensors(int32_t lattice) { return nsens_of(lattice); }
+
+lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_stream, lks_ctx** out)
+{
+    if (!out) return fail(nullptr, LKS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (const char* m = validate_config(cfg)) return fail(nullptr, LKS_EINVAL, m);
+    if (!buf) return fail(nullptr, LKS_EINVAL, "buffers are NULL");
+    if (cfg->lattice == LKS_D2Q25)
+        return fail(nullptr, LKS_EUNSUPPORTED, "D2Q25 is not available in this build");
+    if (!buf->pop[0] || !buf->pop[1] || !buf->sensors || !buf->flags || !buf->sums || !buf->scratch)
+        return fail(nullptr, LKS_EINVAL, "a buffer pointer is NULL");
+    if (buf->pop[0] == buf->pop[1]) return fail(nullptr, LKS_EINVAL, "pop[0] and pop[1] alias");
+    const size_t need = scratch_for(*cfg);
+    if (buf->scratch_bytes < need)
+        return fail(nullptr, LKS_EINVAL,
+                    "scratch too small: need " + std::to_string(need) + " bytes");
+    if (!aligned(buf->scratch, 8) || !aligned(buf->sums, 8))
+        return fail(nullptr, LKS_EINVAL, "scratch and sums must be 8-byte aligned");
+    const size_t sb = store_bytes(cfg->dtype);
+    if (!aligned(buf->pop[0], sb) || !aligned(buf->pop[1], sb) ||
+        !aligned(buf->sensors, sens_bytes(cfg->dtype)))
+        return fail(nullptr, LKS_EINVAL, "population or sensor buffer misaligned for its dtype");
+
+    lks_ctx* c = new (std::nothrow) lks_ctx();
+    if (!c) return fail(nullptr, LKS_EINVAL, "out of host memory");
+    c->cfg = *cfg;
+    c->buf = *buf;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->Q = q_of(cfg->lattice);
+    c->nsens = nsens_of(cfg->lattice);
+    c->n = (long long)cfg->nx * cfg->ny;
+    c->cur = 0;
+    c->steps = 0;
+    c->ready = false;
+    c->chunk = cfg->max_steps < kMaxChunk ? cfg->max_steps : kMaxChunk;
+    c->faults = reinterpret_cast<unsigned long long*>(buf->scratch);
+    c->partials = reinterpret_cast<double*>(static_cast<char*>(buf->scratch) + kHeader);
+
+    // widest vector the row length and buffer alignment allow (or the hint)
+    int vec = cfg->launch_vec > 0 ? cfg->launch_vec : wide_vec(cfg->dtype);
+    const size_t vbytes = sb * vec;
+    if (cfg->nx % vec != 0 || !aligned(buf->pop[0], vbytes) || !aligned(buf->pop[1], vbytes) ||
+        !aligned(buf->sensors, sens_bytes(cfg->dtype) * vec) || !aligned(buf->flags, vec))
+        vec = 1;
+    lks::D2Q9Args& a = c->a9;
+    a.nx = cfg->nx;
+    a.ny = cfg->ny;
+    a.plane = c->n;
+    a.tau = cfg->tau;
+    a.rho0 = cfg->rho0;
+    std::memcpy(a.thr, cfg->thr, sizeof(a.thr));
+    a.mask = cfg->flag_mask;
+    a.g = d2q9_shape(*cfg, vec);
+    *out = c;
+    return LKS_OK;
+}
+
+lks_status lks_init_equilibrium(lks_ctx* c, const double* rho, const double* ux, const double* uy,
+                                const double* T)
+{
+    if (!c) return LKS_EINVAL;
+    if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
+    if (c->cfg.lattice == LKS_D2Q25 && !T) return fail(c, LKS_EINVAL, "T is required on D2Q25");
+    hipError_t e = lks::launch_d2q9_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy,
+                                         c->buf.pop[0], c->stream);
+    if (lks_status s = hip_check(c, e, "init kernel")) return s;
+    if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
+    c->cur = 0;
+    c->steps = 0;
+    c->ready = true;
+    return LKS_OK;
+}
+
+lks_status lks_restore(lks_ctx* c, int32_t pop_index, int64_t steps_done)
+{
+    if (!c) return LKS_EINVAL;
+    if (pop_index != 0 && pop_index != 1) return fail(c, LKS_EINVAL, "pop_index must be 0 or 1");
+    if (steps_done < 0) return fail(c, LKS_EINVAL, "steps_done must be >= 0");
+    if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
+    c->cur = pop_index;
+    c->steps = steps_done;
+    c->ready = true;
+    return LKS_OK;
+}
+
+lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
+{
+    if (!c) return LKS_EINVAL;
+    if (nsteps < 0) return fail(c, LKS_EINVAL, "nsteps must be >= 0");
+    if (fused != 0 && fused != 1) return fail(c, LKS_EINVAL, "fused must be 0 or 1");
+    if (!c->ready) return fail(c, LKS_ESTATE, "step before init_equilibrium or restore");
+    const lks::D2Q9Args& a = c->a9;
+    const int nb = a.g.nblocks;
+    int done = 0;
+    while (done < nsteps) {
+        const int m = (nsteps - done) < c->chunk ? (nsteps - done) : c->chunk;
+        for (int s = 0; s < m; ++s) {
+            double* part = c->partials + (size_t)s * nb * lks::kNsumsHost;
+            void* f = c->buf.pop[c->cur];
+            void* g = c->buf.pop[1 - c->cur];
+            hipError_t e;
+            if (fused) {
+                e = lks::launch_d2q9(c->cfg.dtype, lks::kFused, a, f, g, c->buf.sensors,
+                                     c->buf.flags, part, c->faults, c->stream);
+                if (e == hipSuccess) c->cur = 1 - c->cur;
+            } else {
+                e = lks::launch_d2q9(c->cfg.dtype, lks::kStream, a, f, g, nullptr, nullptr,
+                                     nullptr, nullptr, c->stream);
+                if (e == hipSuccess)
+                    e = lks::launch_d2q9(c->cfg.dtype, lks::kSense, a, g, nullptr, c->buf.sensors,
+                                         c->buf.flags, part, c->faults, c->stream);
+                if (e == hipSuccess)
+                    e = lks::launch_d2q9(c->cfg.dtype, lks::kCollide, a, g, f, nullptr, nullptr,
+                                         nullptr, nullptr, c->stream);
+            }
+            if (lks_status st = hip_check(c, e, "step kernel")) return st;
+        }
+        const double mass_ref = (double)c->n * c->cfg.rho0;
+        hipError_t e = lks::launch_finalize(c->partials, nb, m, c->buf.sums, c->steps,
+                                            c->cfg.max_steps, mass_ref, 0.0, c->stream);
+        if (lks_status st = hip_check(c, e, "finalize kernel")) return st;
+        c->steps += m;
+        done += m;
+    }
+    return LKS_OK;
+}
+
+lks_status lks_current(const lks_ctx* c, int32_t* pop_index, int64_t* steps_done)
+{
+    if (!c) return LKS_EINVAL;
+    if (pop_index) *pop_index = c->cur;
+    if (steps_done) *steps_done = c->steps;
+    return LKS_OK;
+}
+
+lks_status lks_moments(lks_ctx* c, double* rho, double* ux, double* uy, double* T)
+{
+    if (!c) return LKS_EINVAL;
+    if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
+    if (!c->ready) return fail(c, LKS_ESTATE, "moments before init_equilibrium or restore");
+    hipError_t e = lks::launch_d2q9_moments(c->cfg.dtype, c->n, c->cfg.rho0, c->buf.pop[c->cur],
+                                            rho, ux, uy, T, c->stream);
+    return hip_check(c, e, "moments kernel");
+}
+
+lks_status lks_read_host(lks_ctx* c, int32_t what, void* dst, size_t bytes)
+{
+    if (!c) return LKS_EINVAL;
+    if (!dst) return fail(c, LKS_EINVAL, "host_dst is NULL");
+    const void* src = nullptr;
+    size_t size = 0;
+    switch (what) {
+    case 0: src = c->buf.pop[c->cur]; size = (size_t)c->Q * c->n * store_bytes(c->cfg.dtype); break;
+    case 1: src = c->buf.sensors; size = (size_t)c->nsens * c->n * sens_bytes(c->cfg.dtype); break;
+    case 2: src = c->buf.flags; size = (size_t)c->n; break;
+    case 3: src = c->buf.sums; size = (size_t)c->cfg.max_steps * LKS_NSUMS * sizeof(double); break;
+    default: return fail(c, LKS_EINVAL, "what must be 0..3");
+    }
+    if (bytes != size)
+        return fail(c, LKS_EINVAL, "bytes must be " + std::to_string(size));
+    if (lks_status s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync")) return s;
+    return hip_check(c, hipMemcpy(dst, src, size, hipMemcpyDeviceToHost), "copy to host");
+}
+
+lks_status lks_check(lks_ctx* c, int64_t* n_nonpos)
+{
+    if (!c) return LKS_EINVAL;
+    if (lks_status s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync")) return s;
+    unsigned long long nf = 0;
+    if (lks_status s = hip_check(c, hipMemcpy(&nf, c->faults, sizeof(nf), hipMemcpyDeviceToHost),
+                                 "read fault counter"))
+        return s;
+    if (n_nonpos) *n_nonpos = (int64_t)nf;
+    const long long rows = c->steps < c->cfg.max_steps ? c->steps : c->cfg.max_steps;
+    if (rows > 0) {
+        std::string host((size_t)rows * LKS_NSUMS * sizeof(double), '\0');
+        if (lks_status s = hip_check(c, hipMemcpy(&host[0], c->buf.sums, host.size(),
+                                                  hipMemcpyDeviceToHost), "read sums"))
+            return s;
+        const double* h = reinterpret_cast<const double*>(host.data());
+        for (long long r = 0; r < rows; ++r)
+            for (int k = 0; k < 3; ++k)
+                if (std::isnan(h[r * LKS_NSUMS + k]))
+                    return fail(c, LKS_ENAN, "a mass or momentum sum is NaN");
+    }
+    if (nf > 0) return fail(c, LKS_ENONPOS, std::to_string(nf) + " positivity-fault cells");
+    return LKS_OK;
+}
+
+lks_status lks_step_from(lks_ctx* c, const void* src, void* dst)
+{
+    if (!c) return LKS_EINVAL;
+    if (!src || !dst) return fail(c, LKS_EINVAL, "src and dst are required");
+    if (src == dst) return fail(c, LKS_EINVAL, "src and dst must differ");
+    hipError_t e = lks::launch_d2q9(c->cfg.dtype, lks::kFused, c->a9, src, dst, c->buf.sensors,
+                                    c->buf.flags, c->partials, c->faults, c->stream);
+    return hip_check(c, e, "step kernel");
+}
+
+namespace {
+lks_status adjoint_ok(lks_ctx* c)
+{
+    if (c->cfg.lattice != LKS_D2Q9) return fail(c, LKS_EUNSUPPORTED, "the adjoint is D2Q9 only");
+    if (c->cfg.dtype != LKS_F32 && c->cfg.dtype != LKS_F64)
+        return fail(c, LKS_EUNSUPPORTED, "the adjoint needs F32 or F64 storage");
+    return LKS_OK;
+}
+} // namespace
+
+lks_status lks_adjoint_seed_kl(lks_ctx* c, const void* pop_prev, void* lam_out)
+{
+    if (!c) return LKS_EINVAL;
+    if (lks_status s = adjoint_ok(c)) return s;
+    if (!pop_prev || !lam_out) return fail(c, LKS_EINVAL, "pop_prev and lam_out are required");
+    if (pop_prev == lam_out) return fail(c, LKS_EINVAL, "pop_prev and lam_out must differ");
+    return hip_check(c, lks::launch_adj_seed(c->cfg.dtype, c->a9, pop_prev, lam_out, c->stream),
+                     "adjoint seed kernel");
+}
+
+lks_status lks_adjoint_step(lks_ctx* c, const void* pop_prev, const void* lam_in, void* lam_out)
+{
+    if (!c) return LKS_EINVAL;
+    if (lks_status s = adjoint_ok(c)) return s;
+    if (!pop_prev || !lam_in || !lam_out)
+        return fail(c, LKS_EINVAL, "pop_prev, lam_in and lam_out are required");
+    if (lam_in == lam_out || pop_prev == lam_out)
+        return fail(c, LKS_EINVAL, "lam_out must not alias an input");
+    return hip_check(c, lks::launch_adj_step(c->cfg.dtype, c->a9, pop_prev, lam_in, lam_out,
+                                             c->stream),
+                     "adjoint step kernel");
+}
+
+lks_status lks_adjoint_init(lks_ctx* c, const double* rho0, const double* ux0, const double* uy0,
+                            const void* lam0, double* gux, double* guy)
+{
+    if (!c) return LKS_EINVAL;
+    if (lks_status s = adjoint_ok(c)) return s;
+    if (!rho0 || !ux0 || !uy0 || !lam0 || !gux || !guy)
+        return fail(c, LKS_EINVAL, "all arguments are required");
+    return hip_check(c, lks::launch_adj_init(c->cfg.dtype, c->a9, rho0, ux0, uy0, lam0, gux, guy,
+                                             c->stream),
+                     "adjoint init kernel");
+}
+
+lks_status lks_destroy(lks_ctx* c)
+{
+    delete c;
+    return LKS_OK;
+}
+
+const char* lks_status_str(lks_status s)
+{
+    switch (s) {
+    case LKS_OK: return "ok";
+    case LKS_EINVAL: return "invalid argument";
+    case LKS_ESTATE: return "call out of order";
+    case LKS_EHIP: return "HIP runtime error";
+    case LKS_ENONPOS: return "non-positive populations";
+    case LKS_ENAN: return "NaN in global sums";
+    case LKS_EUNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown status";
+}
+
+const char* lks_last_error(const lks_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+lks_status lks_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream)
+{
+    if (!dst || !src || bytes % 16 != 0 || !aligned(dst, 16) || !aligned(src, 16))
+        return fail(nullptr, LKS_EINVAL, "copy probe needs 16-byte aligned pointers and sizes");
+    hipError_t e = lks::launch_copy_probe(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
+    return hip_check(nullptr, e, "copy kernel");
+}
+
+} // extern "C"

@@ -1,0 +1,207 @@
+// lks_device.h -- device-side building blocks shared by the gfx950 kernels:
+// storage conversions, packed vector loads/stores, the KL integrand and
+// wave64 FP64 reductions.  HIP only; included by the kernel sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Occupancy hint for the cell kernels: minimum waves per SIMD the register
+// allocation must allow (0 = let the compiler decide).
+#ifndef LKS_WAVES_PER_EU
+#define LKS_WAVES_PER_EU 0
+#endif
+#if LKS_WAVES_PER_EU > 0
+#define LKS_CELL_KERNEL_ATTR __attribute__((amdgpu_waves_per_eu(LKS_WAVES_PER_EU)))
+#else
+#define LKS_CELL_KERNEL_ATTR
+#endif
+
+// Non-temporal (streaming) stores for outputs that are not re-read by the
+// same step: 1 = use them.
+#ifndef LKS_NT_STORES
+#define LKS_NT_STORES 0
+#endif
+
+namespace lks {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // 4 waves per workgroup
+constexpr int kNsums = 8;
+
+// ---------------------------------------------------------------------------
+// Storage types.  Populations are stored as deviations d = f - w*rho0; the
+// 16-bit formats are raw bit patterns (uint16_t) to keep loads plain.
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+struct f16_t { uint16_t bits; };
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even; NaN stays a (quiet) NaN
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+// v_cvt_f16_f32 rounds to nearest even in the default mode
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+
+template <typename S> struct Store;
+template <> struct Store<double> {
+    using raw = double;
+    using real = double;
+    __device__ static double to_real(raw v) { return v; }
+    __device__ static raw from_real(double v) { return v; }
+};
+template <> struct Store<float> {
+    using raw = float;
+    using real = float;
+    __device__ static float to_real(raw v) { return v; }
+    __device__ static raw from_real(float v) { return v; }
+};
+template <> struct Store<bf16_t> {
+    using raw = uint16_t;
+    using real = float;
+    __device__ static float to_real(raw v) { return bf16_to_f32(v); }
+    __device__ static raw from_real(float v) { return f32_to_bf16_rne(v); }
+};
+template <> struct Store<f16_t> {
+    using raw = uint16_t;
+    using real = float;
+    __device__ static float to_real(raw v) { return f16_to_f32(v); }
+    __device__ static raw from_real(float v) { return f32_to_f16_rne(v); }
+};
+
+// VEC consecutive elements as one aligned memory operation
+template <typename T, int VEC> struct alignas(sizeof(T) * VEC) Pack { T v[VEC]; };
+
+// store of a pack, optionally with the non-temporal hint
+template <typename T, int VEC>
+__device__ __forceinline__ void store_raw_pack(T* __restrict__ p, const Pack<T, VEC>& pk)
+{
+#if LKS_NT_STORES
+    constexpr int bytes = (int)sizeof(T) * VEC;
+    if constexpr (bytes == 16) {
+        using V = __attribute__((ext_vector_type(4))) unsigned int;
+        __builtin_nontemporal_store(__builtin_bit_cast(V, pk), reinterpret_cast<V*>(p));
+    } else if constexpr (bytes == 8) {
+        using V = __attribute__((ext_vector_type(2))) unsigned int;
+        __builtin_nontemporal_store(__builtin_bit_cast(V, pk), reinterpret_cast<V*>(p));
+    } else if constexpr (bytes == 4) {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned int, pk), reinterpret_cast<unsigned int*>(p));
+    } else if constexpr (bytes == 2) {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, pk), reinterpret_cast<unsigned short*>(p));
+    } else {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned char, pk), reinterpret_cast<unsigned char*>(p));
+    }
+#else
+    *reinterpret_cast<Pack<T, VEC>*>(p) = pk;
+#endif
+}
+
+template <typename S, int VEC>
+__device__ __forceinline__ void load_vec(const typename Store<S>::raw* __restrict__ p,
+                                         typename Store<S>::real (&out)[VEC])
+{
+    using raw = typename Store<S>::raw;
+    const Pack<raw, VEC> pk = *reinterpret_cast<const Pack<raw, VEC>*>(p);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) out[k] = Store<S>::to_real(pk.v[k]);
+}
+
+template <typename S, int VEC>
+__device__ __forceinline__ void store_vec(typename Store<S>::raw* __restrict__ p,
+                                          const typename Store<S>::real (&in)[VEC])
+{
+    using raw = typename Store<S>::raw;
+    Pack<raw, VEC> pk;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) pk.v[k] = Store<S>::from_real(in[k]);
+    store_raw_pack(p, pk);
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_pack(T* __restrict__ p, const T (&in)[VEC])
+{
+    Pack<T, VEC> pk;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) pk.v[k] = in[k];
+    store_raw_pack(p, pk);
+}
+
+// ---------------------------------------------------------------------------
+// Arithmetic helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float log1p_r(float x) { return log1pf(x); }
+__device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
+
+// KL integrand phi(x) = (1+x) ln(1+x) - x, so that f ln(f/feq) - f + feq =
+// feq * phi(fneq/feq).  Near 0 the closed form cancels; there the Taylor
+// series sum_{n>=2} (-1)^n x^n / (n(n-1)) is used, truncated after n = 9
+// (relative truncation 2 x^8/90: < 3e-10 for |x| <= 0.1 in FP32 and < 3e-18
+// for |x| <= 0.01 in FP64).
+template <typename R> struct PhiCut;
+template <> struct PhiCut<float> { static constexpr float v = 0.1f; };
+template <> struct PhiCut<double> { static constexpr double v = 0.01; };
+
+template <typename R>
+__device__ __forceinline__ R kl_phi(R x)
+{
+    if (fabs(x) <= PhiCut<R>::v) {
+        R p = R(-1.0 / 72.0);
+        p = p * x + R(1.0 / 56.0);
+        p = p * x + R(-1.0 / 42.0);
+        p = p * x + R(1.0 / 30.0);
+        p = p * x + R(-1.0 / 20.0);
+        p = p * x + R(1.0 / 12.0);
+        p = p * x + R(-1.0 / 6.0);
+        p = p * x + R(0.5);
+        return p * x * x;
+    }
+    return (R(1) + x) * log1p_r(x) - x;
+}
+
+// derivative phi'(x) = ln(1+x) (used by the adjoint seed)
+template <typename R>
+__device__ __forceinline__ R kl_dphi(R x) { return log1p_r(x); }
+
+// ---------------------------------------------------------------------------
+// Reductions: wave64 butterfly in FP64, then across the 4 waves via LDS.
+// Deterministic for a fixed launch shape.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Reduces acc[kNsums] over the block; thread 0 writes out[0..kNsums).
+__device__ __forceinline__ void block_sums(double (&acc)[kNsums], double* __restrict__ out)
+{
+    __shared__ double red[kBlock / kWave][kNsums];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kNsums; ++k) red[wave][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kNsums) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+} // namespace lks

@@ -1,0 +1,90 @@
+// lks_internal.h -- launch interface between the C-ABI layer (lks_api.hip)
+// and the kernel translation units.  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lks {
+
+constexpr int kNsumsHost = 8;   // doubles per partial / per step (LKS_NSUMS)
+
+// Launch shape of the cell kernels: each thread owns `vec` consecutive cells
+// of a row, a 256-thread workgroup spans 256*vec cells of `rows` consecutive
+// rows, and workgroup b covers x-tile (b % tiles_x) of row group (b / tiles_x).
+struct GridShape {
+    int vec;
+    int tiles_x;
+    int rows;
+    int nblocks;
+};
+
+struct D2Q9Args {
+    int nx, ny;
+    long long plane;          // nx * ny
+    double tau;
+    double rho0;
+    double thr[4][2];
+    unsigned mask;
+    GridShape g;
+};
+
+struct D2Q25Args {
+    int nx, ny;
+    long long plane;
+    int bc_x, bc_y;           // 0 periodic, 1 outflow
+    double mu, dt, dx;
+    double rho0;
+    double thr[4][2];
+    unsigned mask;
+    int tile_x, tile_y;       // cells per workgroup tile
+    int tiles_x, tiles_y;
+    int nblocks;
+};
+
+// D2Q9 passes: the fused step and the three passes of the unfused baseline
+enum Pass { kFused = 0, kStream = 1, kSense = 2, kCollide = 3 };
+
+// dtype: 0 f64, 1 f32, 2 bf16, 3 f16 (storage of the deviations)
+hipError_t launch_d2q9(int dtype, int pass, const D2Q9Args& a, const void* fin, void* fout,
+                       void* sens, uint8_t* flags, double* partials,
+                       unsigned long long* faults, hipStream_t s);
+
+hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fout, void* sens,
+                        uint8_t* flags, double* partials, unsigned long long* faults,
+                        hipStream_t s);
+
+// equilibrium initial states from FP64 fields [ny][nx] (n = nx*ny cells)
+hipError_t launch_d2q9_init(int dtype, long long n, double rho0, const double* rho,
+                            const double* ux, const double* uy, void* pop, hipStream_t s);
+hipError_t launch_d2q25_init(int dtype, long long n, double rho0, const double* rho,
+                             const double* ux, const double* uy, const double* T, void* pop,
+                             hipStream_t s);
+
+// FP64 moments of a stored state (T may be null)
+hipError_t launch_d2q9_moments(int dtype, long long n, double rho0, const void* pop, double* rho,
+                               double* ux, double* uy, double* T, hipStream_t s);
+hipError_t launch_d2q25_moments(int dtype, long long n, double rho0, const void* pop,
+                                double* rho, double* ux, double* uy, double* T, hipStream_t s);
+
+// Reduce partials[step][nblocks][8] of nsteps steps into sums rows
+// (row0 + step) mod max_rows; adds the reference mass/energy n_cells*rho0*(1, e_ref).
+hipError_t launch_finalize(const double* partials, int nblocks, int nsteps, double* sums,
+                           long long row0, int max_rows, double mass_ref, double energy_ref,
+                           hipStream_t s);
+
+// adjoint kernels (D2Q9, F32/F64 storage)
+hipError_t launch_adj_seed(int dtype, const D2Q9Args& a, const void* pop_prev, void* lam_out,
+                           hipStream_t s);
+hipError_t launch_adj_step(int dtype, const D2Q9Args& a, const void* pop_prev,
+                           const void* lam_in, void* lam_out, hipStream_t s);
+hipError_t launch_adj_init(int dtype, const D2Q9Args& a, const double* rho0,
+                           const double* ux0, const double* uy0, const void* lam0,
+                           double* gux, double* guy, hipStream_t s);
+
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// clears nwords 8-byte words with a fill kernel
+hipError_t launch_zero(void* p, long long nwords, hipStream_t s);
+
+} // namespace lks

@@ -1,0 +1,251 @@
+"""Thin Python binding of liblks.so (ctypes): argument marshalling only.
+
+Every step of the kinetic path runs in the library's HIP kernels; PyTorch
+provides the device memory (caller-owned buffers) and the stream.  There is no
+CPU fallback: if the library is missing or no GPU is present, calls raise.
+Names follow include/lks.h.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblks.so")
+
+D2Q9, D2Q25 = 9, 25
+F64, F32, BF16, F16 = 0, 1, 2, 3
+PERIODIC, OUTFLOW = 0, 1
+S_KL, S_NEQ, S_PI, S_Q = 1, 2, 4, 8
+NSUMS = 8
+STATUS = {0: "LKS_OK", 1: "LKS_EINVAL", 2: "LKS_ESTATE", 3: "LKS_EHIP", 4: "LKS_ENONPOS",
+          5: "LKS_ENAN", 6: "LKS_EUNSUPPORTED"}
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
+_TORCH_STORE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}
+
+
+class LksError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double),
+                ("dx", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("flag_mask", ctypes.c_uint32), ("launch_rows", ctypes.c_int32),
+                ("thr", (ctypes.c_double * 2) * 4), ("max_steps", ctypes.c_int32),
+                ("launch_vec", ctypes.c_int32)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_void_p * 2), ("sensors", ctypes.c_void_p),
+                ("flags", ctypes.c_void_p), ("sums", ctypes.c_void_p),
+                ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liblks.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_2603_13618_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        sig = {
+            "lks_scratch_bytes": ([ctypes.POINTER(Config)], ctypes.c_size_t),
+            "lks_num_sensors": ([I32], I32),
+            "lks_create": ([ctypes.POINTER(Config), ctypes.POINTER(Buffers), P, ctypes.POINTER(P)], I32),
+            "lks_init_equilibrium": ([P, P, P, P, P], I32),
+            "lks_restore": ([P, I32, I64], I32),
+            "lks_step": ([P, I32, I32], I32),
+            "lks_step_from": ([P, P, P], I32),
+            "lks_current": ([P, ctypes.POINTER(I32), ctypes.POINTER(I64)], I32),
+            "lks_moments": ([P, P, P, P, P], I32),
+            "lks_read_host": ([P, I32, P, ctypes.c_size_t], I32),
+            "lks_check": ([P, ctypes.POINTER(I64)], I32),
+            "lks_adjoint_seed_kl": ([P, P, P], I32),
+            "lks_adjoint_step": ([P, P, P, P], I32),
+            "lks_adjoint_init": ([P, P, P, P, P, P, P], I32),
+            "lks_destroy": ([P], I32),
+            "lks_status_str": ([I32], ctypes.c_char_p),
+            "lks_last_error": ([P], ctypes.c_char_p),
+            "lks_copy_probe": ([P, P, ctypes.c_size_t, P], I32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, dx=1.0,
+                bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
+                launch_rows=0, launch_vec=0):
+    c = Config()
+    c.lattice, c.nx, c.ny = lattice, nx, ny
+    c.dtype = DTYPES[dtype] if isinstance(dtype, str) else dtype
+    c.bc_x, c.bc_y = bc
+    c.tau, c.mu, c.dt, c.dx, c.rho0 = tau, mu, dt, dx, rho0
+    c.flag_mask = flag_mask
+    c.launch_rows = launch_rows
+    t = np.full((4, 2), math.inf) if thr is None else np.asarray(thr, np.float64).reshape(4, 2)
+    for s in range(4):
+        c.thr[s][0], c.thr[s][1] = float(t[s, 0]), float(t[s, 1])
+    c.max_steps = max_steps
+    c.launch_vec = launch_vec
+    return c
+
+
+def scratch_bytes(cfg):
+    return int(lib().lks_scratch_bytes(ctypes.byref(cfg)))
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        msg = lib().lks_last_error(ctx).decode()
+        raise LksError(status, msg)
+
+
+class Lattice:
+    """One simulation context with torch-owned device buffers.
+
+    Attributes: pop (2 tensors [Q, ny, nx]), sensors [nsens, ny, nx],
+    flags [ny, nx] uint8, sums [max_steps, 8] float64.
+    """
+
+    def __init__(self, lattice=D2Q9, nx=64, ny=64, dtype="f32", tau=0.6, mu=0.0, dt=0.0, dx=1.0,
+                 bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
+                 launch_rows=0, launch_vec=0, device="cuda"):
+        self.device = torch.device(device)
+        self.cfg = make_config(lattice, nx, ny, dtype, tau, mu, dt, dx, bc, rho0, thr, flag_mask,
+                               max_steps, launch_rows, launch_vec)
+        self.Q = lattice
+        self.nx, self.ny = nx, ny
+        self.dtype = self.cfg.dtype
+        nsens = int(lib().lks_num_sensors(lattice))
+        sdt = torch.float64 if self.dtype == F64 else torch.float32
+        tdt = _TORCH_STORE[self.dtype]
+        dev = self.device
+        self.pop = [torch.zeros((lattice, ny, nx), dtype=tdt, device=dev) for _ in range(2)]
+        self.sensors = torch.zeros((nsens, ny, nx), dtype=sdt, device=dev)
+        self.flags = torch.zeros((ny, nx), dtype=torch.uint8, device=dev)
+        self.sums = torch.zeros((max_steps, NSUMS), dtype=torch.float64, device=dev)
+        nsb = scratch_bytes(self.cfg)
+        if nsb == 0:
+            raise LksError(1, "invalid configuration")
+        self.scratch = torch.zeros(nsb, dtype=torch.uint8, device=dev)
+        self.buf = Buffers()
+        self.buf.pop[0] = self.pop[0].data_ptr()
+        self.buf.pop[1] = self.pop[1].data_ptr()
+        self.buf.sensors = self.sensors.data_ptr()
+        self.buf.flags = self.flags.data_ptr()
+        self.buf.sums = self.sums.data_ptr()
+        self.buf.scratch = self.scratch.data_ptr()
+        self.buf.scratch_bytes = nsb
+        self.ctx = ctypes.c_void_p()
+        st = lib().lks_create(ctypes.byref(self.cfg), ctypes.byref(self.buf),
+                              _stream_handle(dev), ctypes.byref(self.ctx))
+        _check(st, None)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx and _lib is not None:
+            _lib.lks_destroy(ctx)
+            self.ctx = None
+
+    def _field(self, a):
+        if a is None:
+            return None
+        t = torch.as_tensor(a, dtype=torch.float64)
+        return t.to(self.device).contiguous()
+
+    def init(self, rho, ux, uy, T=None):
+        """Equilibrium initial state of FP64 fields [ny, nx] (numpy or torch)."""
+        self._init_fields = [self._field(a) for a in (rho, ux, uy, T)]
+        f = self._init_fields
+        _check(lib().lks_init_equilibrium(self.ctx, _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
+                                          _ptr(f[3])), self.ctx)
+
+    def restore(self, state, steps_done=0):
+        """Copy a state [Q, ny, nx] (storage dtype) into pop[0] and resume from it."""
+        self.pop[0].copy_(torch.as_tensor(state).to(self.device, self.pop[0].dtype))
+        _check(lib().lks_restore(self.ctx, 0, int(steps_done)), self.ctx)
+
+    def step(self, nsteps=1, fused=True):
+        _check(lib().lks_step(self.ctx, int(nsteps), 1 if fused else 0), self.ctx)
+
+    def step_from(self, src, dst):
+        """One fused step from the state tensor src into dst (step count unchanged)."""
+        _check(lib().lks_step_from(self.ctx, _ptr(src), _ptr(dst)), self.ctx)
+
+    def current(self):
+        i, n = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().lks_current(self.ctx, ctypes.byref(i), ctypes.byref(n)), self.ctx)
+        return i.value, n.value
+
+    @property
+    def state(self):
+        return self.pop[self.current()[0]]
+
+    def moments(self):
+        """(rho, ux, uy, T) FP64 device tensors of the current state."""
+        out = [torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+               for _ in range(4)]
+        _check(lib().lks_moments(self.ctx, *[_ptr(t) for t in out]), self.ctx)
+        return out
+
+    def check(self):
+        """Synchronise; returns the positivity-fault count (raises on NaN sums)."""
+        n = ctypes.c_int64()
+        st = lib().lks_check(self.ctx, ctypes.byref(n))
+        if st not in (0, 4):
+            _check(st, self.ctx)
+        return n.value
+
+    def read_host(self, what):
+        """Synchronous copy to a numpy array through lks_read_host (what 0..3)."""
+        src = [self.state, self.sensors, self.flags, self.sums][what]
+        if src.dtype == torch.bfloat16:
+            out = np.empty(src.shape, np.uint16)
+        else:
+            out = np.empty(src.shape, {torch.float64: np.float64, torch.float32: np.float32,
+                                       torch.float16: np.float16, torch.uint8: np.uint8}[src.dtype])
+        _check(lib().lks_read_host(self.ctx, what, out.ctypes.data_as(ctypes.c_void_p),
+                                   out.nbytes), self.ctx)
+        return out
+
+    # ---- adjoint (D2Q9) ----
+    def adjoint_seed_kl(self, pop_prev, lam_out):
+        _check(lib().lks_adjoint_seed_kl(self.ctx, _ptr(pop_prev), _ptr(lam_out)), self.ctx)
+
+    def adjoint_step(self, pop_prev, lam_in, lam_out):
+        _check(lib().lks_adjoint_step(self.ctx, _ptr(pop_prev), _ptr(lam_in), _ptr(lam_out)),
+               self.ctx)
+
+    def adjoint_init(self, rho0, ux0, uy0, lam0, gux, guy):
+        _check(lib().lks_adjoint_init(self.ctx, _ptr(rho0), _ptr(ux0), _ptr(uy0), _ptr(lam0),
+                                      _ptr(gux), _ptr(guy)), self.ctx)
+
+
+def copy_probe(dst, src):
+    """Device copy of src into dst (same byte size) with the library's copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    _check(lib().lks_copy_probe(_ptr(dst), _ptr(src), nbytes, _stream_handle(src.device)))
+

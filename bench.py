@@ -1,0 +1,249 @@
+"""Throughput of the fused D2Q9 kinetic step with local kinetic sensors on one
+MI355X, against the unfused passes, the HBM roofline and the FP64 CPU oracle.
+
+Workload: smooth random field (seed 0, 16 Fourier modes), D2Q9 BGK, 4096x4096
+periodic, tau = 0.52, FP32 deviation storage; one step = pull streaming +
+moments + equilibrium + S_KL, S_NEQ, S_PI + refinement flags + BGK collision +
+FP64 global sums, all in one kernel (plus one small reduction kernel per 64
+steps).  Inputs are resident in HBM before the timed region starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--forms]
+    python bench.py --mode kernel --steps 5      # short run for profilers
+    python bench.py --mode copy                  # copy-kernel yardstick only
+
+Prints ONE JSON line (the last line of stdout).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, vendor figure
+BYTES_F32_FUSED = 85            # 9 x 4 read + 9 x 4 written + 3 x 4 sensors + 1 flag
+BYTES_F32_PLAIN = 193           # stream 36 + 36, sensors 36 + 13, collide 36 + 36
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2q9_fused_f32_4096.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_13618_amd", "csrc", "d2q9.hip")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-steps", type=int, default=8)
+    p.add_argument("--forms", action="store_true",
+                   help="also time the BF16/FP16 storage forms on the 8192^2 workload")
+    p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
+    return p.parse_args()
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for name in ("d2q9.hip", "lks_device.h"):
+        with open(os.path.join(ROOT, "paper_2603_13618_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_entry(n_cells):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary, or None if absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_hash() or t.get("cells") != n_cells:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design note, not a measured configuration.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_13618_amd import inputs, lks, workloads
+
+    wl = workloads.SMOOTH_4096
+    n = wl["nx"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    if args.mode == "copy":
+        nbytes = 9 * n * n * 4
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        lks.copy_probe(b, a)
+        torch.cuda.synchronize()
+        s, e = ev(), ev()
+        reps = 10
+        s.record()
+        for _ in range(reps):
+            lks.copy_probe(b, a)
+        e.record()
+        torch.cuda.synchronize()
+        t = s.elapsed_time(e) / reps * 1e-3
+        print(json.dumps({"mode": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                          "GBps": 2 * nbytes / t / 1e9, "us": t * 1e6}))
+        return
+
+    rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+    lat = lks.Lattice(9, n, n, "f32", tau=wl["tau"], thr=wl["thr"], flag_mask=wl["flag_mask"],
+                      max_steps=max(args.steps, 1), device=dev)
+    lat.init(rho, ux, uy)
+
+    if args.mode == "kernel":
+        lat.step(args.steps)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "kernel", "steps": args.steps}))
+        return
+
+    # ---- warmup, then the timed region: K fused steps on the library's stream
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    s, e = ev(), ev()
+    s.record()
+    lat.step(args.steps)
+    e.record()
+    torch.cuda.synchronize()
+    t_step = s.elapsed_time(e) / args.steps * 1e-3
+    faults = lat.check()
+    mlups = n * n / t_step / 1e6
+
+    # ---- the fused kernel alone: back-to-back launches between the two
+    #      state buffers, bracketed by events on the same stream
+    reps = max(args.steps, 10)
+    src, dst = lat.pop[lat.current()[0]], lat.pop[1 - lat.current()[0]]
+    lat.step_from(src, dst)
+    torch.cuda.synchronize()
+    s.record()
+    for r in range(reps):
+        lat.step_from(src, dst) if r % 2 == 0 else lat.step_from(dst, src)
+    e.record()
+    torch.cuda.synchronize()
+    t_kernel = s.elapsed_time(e) / reps * 1e-3
+    achieved = BYTES_F32_FUSED * n * n / t_kernel / 1e9
+    traffic = traffic_entry(n * n)
+
+    # ---- the unfused baseline (three passes per step) on the same state
+    lat.init(rho, ux, uy)
+    lat.step(2, fused=False)
+    torch.cuda.synchronize()
+    ps = max(args.steps // 4, 5)
+    s.record()
+    lat.step(ps, fused=False)
+    e.record()
+    torch.cuda.synchronize()
+    t_plain = s.elapsed_time(e) / ps * 1e-3
+
+    out = {
+        "metric": "MLUPS incl. sensor + achieved HBM GB/s (% roofline), fused FP32 vs plain",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "D2Q9 BGK 4096x4096 periodic, FP32 deviation storage, fused pull-stream "
+                        "+ collide + S_KL/S_NEQ/S_PI + flags + FP64 sums, tau=0.52, smooth "
+                        "random field (seed 0, 16 modes)",
+            "grid": [n, n], "tau": wl["tau"], "lattice": "D2Q9",
+        },
+        "achieved_GBps": round(BYTES_F32_FUSED * n * n / t_step / 1e9, 1),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "kernel": "d2q9_kernel<float,4,fused>",
+            "bytes_per_launch": BYTES_F32_FUSED * n * n,
+            "kernel_us": round(t_kernel * 1e6, 2),
+        },
+        "plain": {
+            "MLUPS": round(n * n / t_plain / 1e6, 1),
+            "ms_per_step": round(t_plain * 1e3, 4),
+            "GBps_model": round(BYTES_F32_PLAIN * n * n / t_plain / 1e9, 1),
+            "fused_speedup": round(t_plain / t_step, 3),
+        },
+        "positivity_faults": faults,
+    }
+
+    if args.forms:
+        out["forms"] = time_forms(torch, lks, inputs, workloads, dev, ev)
+
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps, rho, ux, uy, wl)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def time_forms(torch, lks, inputs, workloads, dev, ev):
+    """BF16 / FP16 deviation storage on the 8192^2 smooth field (timing only)."""
+    wl = workloads.SMOOTH_8192
+    n = wl["nx"]
+    rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+    res = {}
+    for dtype, nbytes in (("bf16", 49), ("f16", 49), ("f32", 85)):
+        lat = lks.Lattice(9, n, n, dtype, tau=wl["tau"], thr=wl["thr"] or workloads.SMOOTH_4096["thr"],
+                          flag_mask=wl["flag_mask"], max_steps=64, device=dev)
+        lat.init(rho, ux, uy)
+        lat.step(5)
+        torch.cuda.synchronize()
+        s, e = ev(), ev()
+        k = 40
+        s.record()
+        lat.step(k)
+        e.record()
+        torch.cuda.synchronize()
+        t = s.elapsed_time(e) / k * 1e-3
+        res[dtype] = {"MLUPS": round(n * n / t / 1e6, 1), "GBps_model": round(nbytes * n * n / t / 1e9, 1),
+                      "bytes_per_lup": nbytes, "grid": [n, n]}
+        del lat
+        torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(steps, rho, ux, uy, wl):
+    """The FP64 oracle on the host cores: the full 4096^2 grid for a few steps."""
+    import oracle
+    threads = os.cpu_count() or 1
+    f0 = oracle.equilibrium(9, rho, ux, uy)
+    oracle.run(9, f0, 1, tau=wl["tau"], nthreads=threads)          # page-in
+    t0 = time.perf_counter()
+    oracle.run(9, f0, steps, tau=wl["tau"], thr=wl["thr"], mask=wl["flag_mask"], nthreads=threads)
+    t = time.perf_counter() - t0
+    n = rho.size
+    return {"value": round(n * steps / t / 1e6, 2), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"FP64 C oracle (OpenMP), full {rho.shape[1]}x{rho.shape[0]} grid, {steps} "
+                      f"steps of the same workload, {t:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

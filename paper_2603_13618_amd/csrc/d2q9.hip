@@ -73,6 +73,115 @@ __device__ __forceinline__ void pull_row(const typename Store<S>::raw* __restric
     }
 }
 
+// Per-cell result of the sensor part of the update.
+template <typename R> struct CellSense {
+    R kl, neq, pi;
+    bool fault;
+};
+
+// One cell: moments, equilibrium, sensors and (if COLLIDE) the BGK collision
+// of the pre-collision deviations d[0..8] in place.
+template <typename R, bool SENSE, bool COLLIDE>
+__device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau, R& drho_out,
+                                                    R& jx_out, R& jy_out)
+{
+    // moments of the deviation form: rho - rho0 = sum d, j = sum c d
+    const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    const R jx = (d[6] + d[7] + d[8]) - (d[0] + d[1] + d[2]);
+    const R jy = (d[2] + d[5] + d[8]) - (d[0] + d[3] + d[6]);
+    const R rho = rho0 + drho;
+    const R irho = rcp(rho);
+    const R ux = jx * irho, uy = jy * irho;
+    // f^eq_i - w_i rho0 = w_i [(rho - rho0) + rho (3 cu + 9/2 cu^2 - 3/2 u^2)]
+    const R base = drho - R(1.5) * rho * (ux * ux + uy * uy);
+    R deq[9];
+    // corners c = (+-1, +-1)
+#pragma unroll
+    for (int i = 0; i < 9; i += 2) {
+        if (i == 4) continue;
+        const R cu = R(cx9(i)) * ux + R(cy9(i)) * uy;
+        deq[i] = R(1.0 / 36.0) * (base + rho * (cu * (R(3) + R(4.5) * cu)));
+    }
+    // Axis pairs from their sum (even in u) and the momentum they must carry:
+    // this closes sum_i c_i f^eq_i = j exactly up to the last rounding, so no
+    // bias from the rounded weights is fed back by the collision.
+    {
+        const R sx = R(1.0 / 9.0) * (R(2) * base + R(9) * rho * ux * ux);
+        const R dx = jx - ((deq[6] + deq[8]) - (deq[0] + deq[2]));
+        deq[7] = R(0.5) * (sx + dx);
+        deq[1] = R(0.5) * (sx - dx);
+        const R sy = R(1.0 / 9.0) * (R(2) * base + R(9) * rho * uy * uy);
+        const R dy = jy - ((deq[2] + deq[8]) - (deq[0] + deq[6]));
+        deq[5] = R(0.5) * (sy + dy);
+        deq[3] = R(0.5) * (sy - dy);
+    }
+    // rest population closes the mass
+    deq[4] = drho - (((deq[0] + deq[1]) + (deq[2] + deq[3])) + ((deq[5] + deq[6]) + (deq[7] + deq[8])));
+
+    CellSense<R> out{R(0), R(0), R(0), false};
+    if constexpr (SENSE) {
+        R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
+        R xmax = R(0), xmin = R(0), feqmin = R(0);
+        R xs[9], fe[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const R fneq = d[i] - deq[i];
+            const R feq = w9<R>(i) * rho0 + deq[i];
+            const R x = fneq * rcp(feq);
+            xs[i] = x;
+            fe[i] = feq;
+            // S_KL term feq phi(x) = fneq x p(x) on the series branch
+            kl += (fneq * x) * kl_series(x);
+            xmax = i == 0 ? fabs(x) : fmax(xmax, fabs(x));
+            xmin = i == 0 ? x : fmin(xmin, x);
+            feqmin = i == 0 ? feq : fmin(feqmin, feq);
+            neq += fabs(fneq);
+            if (cx9(i) != 0) pxx += fneq;
+            if (cy9(i) != 0) pyy += fneq;
+            if (cx9(i) * cy9(i) != 0) pxy += R(cx9(i) * cy9(i)) * fneq;
+            if constexpr (COLLIDE) d[i] -= inv_tau * fneq;
+        }
+        if (!(xmax <= KlCut<R>::v)) {       // rare: far from equilibrium (or NaN)
+            kl = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) kl += fe[i] * kl_phi(xs[i]);
+        }
+        out.fault = !(feqmin > R(0)) || !(xmin > R(-1)) || !(kl == kl);
+        out.kl = out.fault ? R(INFINITY) : kl;
+        out.neq = neq;
+        out.pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+    } else if constexpr (COLLIDE) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] -= inv_tau * (d[i] - deq[i]);
+    }
+    drho_out = drho;
+    jx_out = jx;
+    jy_out = jy;
+    return out;
+}
+
+template <typename S, int VEC, bool PULL>
+__device__ __forceinline__ void load_row(const typename Store<S>::raw* __restrict__ fin, long long plane,
+                                         int y, int nx, int ny, int x0, bool active, int lane,
+                                         typename Store<S>::real (&d)[9][VEC])
+{
+    using R = typename Store<S>::real;
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int cx = PULL ? cx9(i) : 0;
+        constexpr int cy = PULL ? cy9(i) : 0;
+        int ys = y - cy;
+        ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+        R v[VEC];
+        pull_row<cx, S, VEC>(fin + i * plane + (long long)ys * nx, x0, nx, active, lane, v);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) d[i][k] = v[k];
+    });
+}
+
+// One workgroup: `rows` consecutive rows of one x-tile.  The next row's
+// populations are loaded before the current row is computed, so each wave
+// keeps a row of loads in flight behind its arithmetic.
 template <typename S, int VEC, int PASS>
 __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
     D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
@@ -80,7 +189,6 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
     double* __restrict__ partials, unsigned long long* __restrict__ faults)
 {
     using R = typename Store<S>::real;
-    using raw = typename Store<S>::raw;
     constexpr bool PULL = (PASS == kFused || PASS == kStream);
     constexpr bool SENSE = (PASS == kFused || PASS == kSense);
     constexpr bool COLLIDE = (PASS == kFused || PASS == kCollide);
@@ -92,6 +200,8 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
     const int rg = blockIdx.x / a.g.tiles_x;
     const int x0 = (tx * kBlock + threadIdx.x) * VEC;
     const bool active = x0 < nx;
+    const int y0 = rg * a.g.rows;
+    const int y1 = min(y0 + a.g.rows, ny);
 
     const R rho0 = R(a.rho0);
     const R inv_tau = R(1.0 / a.tau);
@@ -106,95 +216,34 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
     for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
     unsigned nfault = 0;
 
-    for (int r = 0; r < a.g.rows; ++r) {
-        const int y = rg * a.g.rows + r;
-        if (y >= ny) break;                       // uniform across the workgroup
-        R d[9][VEC];                              // d[i][cell]
-        static_for<9>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int cx = PULL ? cx9(i) : 0;
-            constexpr int cy = PULL ? cy9(i) : 0;
-            int ys = y - cy;
-            ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-            R v[VEC];
-            pull_row<cx, S, VEC>(fin + i * plane + (long long)ys * nx, x0, nx, active, lane, v);
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) d[i][k] = v[k];
-        });
+    R cur[9][VEC];
+    if (y0 < y1) load_row<S, VEC, PULL>(fin, plane, y0, nx, ny, x0, active, lane, cur);
+    for (int y = y0; y < y1; ++y) {                 // uniform across the workgroup
+        R nxt[9][VEC];
+        if (y + 1 < y1) load_row<S, VEC, PULL>(fin, plane, y + 1, nx, ny, x0, active, lane, nxt);
         const long long off = (long long)y * nx + x0;
 
         if constexpr (PASS == kStream) {
             if (active) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, d[i]);
+                for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, cur[i]);
             }
-            continue;
         } else {
             R s_kl[VEC], s_neq[VEC], s_pi[VEC];
             uint8_t fl[VEC];
+            R rsum[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
             for (int k = 0; k < VEC; ++k) {
-                // moments of the pre-collision populations (deviation form)
-                R drho = R(0), jx = R(0), jy = R(0);
+                R dc[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    drho += d[i][k];
-                    if (cx9(i) != 0) jx += R(cx9(i)) * d[i][k];
-                    if (cy9(i) != 0) jy += R(cy9(i)) * d[i][k];
-                }
-                const R rho = rho0 + drho;
-                const R irho = rcp(rho);
-                const R ux = jx * irho, uy = jy * irho;
-                const R usq15 = R(1.5) * (ux * ux + uy * uy);
-                // equilibrium deviations
-                // f^eq_i - w_i rho0 = w_i [(rho - rho0) + rho (3cu + 9/2 cu^2 - 3/2 u^2)]
-                R deq[9];
+                for (int i = 0; i < 9; ++i) dc[i] = cur[i][k];
+                R drho, jx, jy;
+                const CellSense<R> cs = cell_update<R, SENSE, COLLIDE>(dc, rho0, inv_tau, drho, jx, jy);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const R cu = R(cx9(i)) * ux + R(cy9(i)) * uy;
-                    const R P = cu * (R(3) + R(4.5) * cu) - usq15;
-                    deq[i] = w9<R>(i) * (drho + rho * P);
-                }
-                // The rounded weights make sum_i c_i f^eq_i differ from rho u by a
-                // relative ~1e-8 in FP32, a bias that the collision would feed back
-                // every step.  Close the x- and y-momentum on the axis pairs and the
-                // mass on the rest population (exact-arithmetic no-ops).
-                {
-                    const R rx = jx - ((deq[6] + deq[7] + deq[8]) - (deq[0] + deq[1] + deq[2]));
-                    const R ry = jy - ((deq[2] + deq[5] + deq[8]) - (deq[0] + deq[3] + deq[6]));
-                    deq[7] += R(0.5) * rx;
-                    deq[1] -= R(0.5) * rx;
-                    deq[5] += R(0.5) * ry;
-                    deq[3] -= R(0.5) * ry;
-                    R rest = R(0);
-#pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        if (i != 4) rest += deq[i];
-                    deq[4] = drho - rest;
-                }
-                R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
-                bool fault = false;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const int cx = cx9(i), cy = cy9(i);
-                    const R fneq = d[i][k] - deq[i];
-                    if constexpr (SENSE) {
-                        const R feq = w9<R>(i) * rho0 + deq[i];
-                        const R f = w9<R>(i) * rho0 + d[i][k];
-                        fault |= !(f > R(0)) || !(feq > R(0));
-                        kl += feq * kl_phi(fneq * rcp(feq));
-                        neq += fabs(fneq);
-                        if (cx != 0) pxx += fneq;
-                        if (cy != 0) pyy += fneq;
-                        if (cx * cy != 0) pxy += R(cx * cy) * fneq;
-                    }
-                    if constexpr (COLLIDE) d[i][k] -= inv_tau * fneq;
-                }
+                for (int i = 0; i < 9; ++i) cur[i][k] = dc[i];
                 if constexpr (SENSE) {
-                    const R spi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
-                    if (fault) kl = R(INFINITY);
                     int level = 0;
-                    const R sv[3] = {kl, neq, spi};
+                    const R sv[3] = {cs.kl, cs.neq, cs.pi};
 #pragma unroll
                     for (int s = 0; s < 3; ++s) {
                         if (a.mask & (1u << s)) {
@@ -202,25 +251,33 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
                             level = l > level ? l : level;
                         }
                     }
-                    fl[k] = fault ? uint8_t(0x82) : uint8_t(level);
-                    s_kl[k] = kl;
-                    s_neq[k] = neq;
-                    s_pi[k] = spi;
+                    fl[k] = cs.fault ? uint8_t(0x82) : uint8_t(level);
+                    s_kl[k] = cs.kl;
+                    s_neq[k] = cs.neq;
+                    s_pi[k] = cs.pi;
                     if (active) {
-                        acc[0] += (double)drho;
-                        acc[1] += (double)jx;
-                        acc[2] += (double)jy;
-                        acc[4] += (double)kl;
-                        acc[5] += (double)neq;
-                        acc[6] += (double)spi;
-                        nfault += fault ? 1u : 0u;
+                        rsum[0] += drho;
+                        rsum[1] += jx;
+                        rsum[2] += jy;
+                        rsum[3] += cs.kl;
+                        rsum[4] += cs.neq;
+                        rsum[5] += cs.pi;
+                        nfault += cs.fault ? 1u : 0u;
                     }
                 }
+            }
+            if constexpr (SENSE) {
+                acc[0] += (double)rsum[0];
+                acc[1] += (double)rsum[1];
+                acc[2] += (double)rsum[2];
+                acc[4] += (double)rsum[3];
+                acc[5] += (double)rsum[4];
+                acc[6] += (double)rsum[5];
             }
             if (active) {
                 if constexpr (COLLIDE) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, d[i]);
+                    for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, cur[i]);
                 }
                 if constexpr (SENSE) {
                     store_pack<R, VEC>(sens + off, s_kl);
@@ -230,6 +287,10 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
                 }
             }
         }
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) cur[i][k] = nxt[i][k];
     }
     if constexpr (SENSE) {
         if (nfault) atomicAdd(faults, (unsigned long long)nfault);

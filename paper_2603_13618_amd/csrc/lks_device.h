@@ -143,28 +143,44 @@ __device__ __forceinline__ float log1p_r(float x) { return log1pf(x); }
 __device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
 
 // KL integrand phi(x) = (1+x) ln(1+x) - x, so that f ln(f/feq) - f + feq =
-// feq * phi(fneq/feq).  Near 0 the closed form cancels; there the Taylor
-// series sum_{n>=2} (-1)^n x^n / (n(n-1)) is used, truncated after n = 9
-// (relative truncation 2 x^8/90: < 3e-10 for |x| <= 0.1 in FP32 and < 3e-18
-// for |x| <= 0.01 in FP64).
-template <typename R> struct PhiCut;
-template <> struct PhiCut<float> { static constexpr float v = 0.1f; };
-template <> struct PhiCut<double> { static constexpr double v = 0.01; };
+// feq * phi(fneq/feq) = fneq * x * p(x) with x = fneq/feq and p(x) = phi(x)/x^2.
+// Near 0 the closed form cancels; there the Taylor series
+// p(x) = sum_{n>=2} (-1)^n x^(n-2) / (n(n-1)) is used for |x| <= KlCut:
+// truncated after n = 7 in FP32 (relative truncation 2 x^6/56 < 4e-8 at
+// |x| = 0.1) and after n = 9 in FP64 (2 x^8/90 < 3e-18 at |x| = 0.01).
+template <typename R> struct KlCut;
+template <> struct KlCut<float> { static constexpr float v = 0.1f; };
+template <> struct KlCut<double> { static constexpr double v = 0.01; };
 
+__device__ __forceinline__ float kl_series(float x)
+{
+    float p = -1.0f / 42.0f;
+    p = p * x + 1.0f / 30.0f;
+    p = p * x + -1.0f / 20.0f;
+    p = p * x + 1.0f / 12.0f;
+    p = p * x + -1.0f / 6.0f;
+    p = p * x + 0.5f;
+    return p;
+}
+
+__device__ __forceinline__ double kl_series(double x)
+{
+    double p = -1.0 / 72.0;
+    p = p * x + 1.0 / 56.0;
+    p = p * x + -1.0 / 42.0;
+    p = p * x + 1.0 / 30.0;
+    p = p * x + -1.0 / 20.0;
+    p = p * x + 1.0 / 12.0;
+    p = p * x + -1.0 / 6.0;
+    p = p * x + 0.5;
+    return p;
+}
+
+// phi(x) on either branch
 template <typename R>
 __device__ __forceinline__ R kl_phi(R x)
 {
-    if (fabs(x) <= PhiCut<R>::v) {
-        R p = R(-1.0 / 72.0);
-        p = p * x + R(1.0 / 56.0);
-        p = p * x + R(-1.0 / 42.0);
-        p = p * x + R(1.0 / 30.0);
-        p = p * x + R(-1.0 / 20.0);
-        p = p * x + R(1.0 / 12.0);
-        p = p * x + R(-1.0 / 6.0);
-        p = p * x + R(0.5);
-        return p * x * x;
-    }
+    if (fabs(x) <= KlCut<R>::v) return x * x * kl_series(x);
     return (R(1) + x) * log1p_r(x) - x;
 }
 

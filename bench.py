@@ -38,10 +38,14 @@ def parse():
     p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-steps", type=int, default=8)
+    p.add_argument("--cpu-steps", type=int, default=40)
     p.add_argument("--forms", action="store_true",
                    help="also time the BF16/FP16 storage forms on the 8192^2 workload")
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
+    p.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                   help="assemble the traffic summary from four rocprofv3 --pmc output "
+                        "directories (FETCH_SIZE and WRITE_SIZE of '--mode kernel', then of "
+                        "'--mode copy') and write it under profiles/")
     return p.parse_args()
 
 
@@ -65,8 +69,69 @@ def traffic_entry(n_cells):
     return t.get("bytes_per_launch")
 
 
+def _pmc_mean(directory, counter, kernel_prefix):
+    """Mean per-dispatch value of a counter for kernels whose name starts with
+    kernel_prefix, from a rocprofv3 counter_collection.csv."""
+    import csv
+    import glob
+    vals = []
+    for path in glob.glob(os.path.join(directory, "*counter_collection.csv")):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter and r["Kernel_Name"].startswith(kernel_prefix):
+                    vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} samples for {kernel_prefix} under {directory}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def assemble_traffic(dirs):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the fused kernel, each
+    scaled by the ratio of the copy kernel's known bytes to what the same
+    counter reads for it."""
+    from paper_2603_13618_amd import workloads
+    n = workloads.SMOOTH_4096["nx"]
+    copy_bytes = 9 * n * n * 4
+    fetch, nf = _pmc_mean(dirs[0], "FETCH_SIZE", "d2q9_kernel")
+    write, nw = _pmc_mean(dirs[1], "WRITE_SIZE", "d2q9_kernel")
+    cfetch, _ = _pmc_mean(dirs[2], "FETCH_SIZE", "copy_kernel")
+    cwrite, _ = _pmc_mean(dirs[3], "WRITE_SIZE", "copy_kernel")
+    kf = copy_bytes / (cfetch * 1024.0)
+    kw = copy_bytes / (cwrite * 1024.0)
+    read_b = fetch * 1024.0 * kf
+    write_b = write * 1024.0 * kw
+    out = {
+        "kernel": "d2q9_kernel<float,4,fused>", "cells": n * n, "kernel_hash": kernel_hash(),
+        "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
+        "copy_fetch_kib": cfetch, "copy_write_kib": cwrite, "copy_bytes_each_way": copy_bytes,
+        "fetch_scale": kf, "write_scale": kw,
+        "read_bytes_per_launch": read_b, "write_bytes_per_launch": write_b,
+        "bytes_per_launch": read_b + write_b,
+        "algorithmic_bytes_per_launch": BYTES_F32_FUSED * n * n,
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE -T -d <dir> -o fetch --output-format csv -- "
+            "python bench.py --mode kernel --steps 3",
+            "rocprofv3 --pmc WRITE_SIZE -T -d <dir> -o write --output-format csv -- "
+            "python bench.py --mode kernel --steps 3",
+            "rocprofv3 --pmc FETCH_SIZE -T -d <dir> -o cfetch --output-format csv -- "
+            "python bench.py --mode copy",
+            "rocprofv3 --pmc WRITE_SIZE -T -d <dir> -o cwrite --output-format csv -- "
+            "python bench.py --mode copy",
+            "python bench.py --traffic-from <fetch dir> <write dir> <copy fetch dir> "
+            "<copy write dir>",
+        ],
+    }
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        assemble_traffic(args.traffic_from)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a measured configuration.",

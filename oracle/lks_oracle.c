@@ -69,7 +69,19 @@ typedef struct {
     double xi[ORC_MAXQ1];   /* nodes of the rule with weight exp(-x^2/2)    */
     double w[ORC_MAXQ1];    /* normalised weights, sum = 1                  */
     double v[ORC_MAXQ1];    /* physical velocity component sqrt(T_ref)*xi   */
+    double he[ORC_MAXQ1][ORC_MAXQ1]; /* He_n(xi_a) / n!, filled by rule_finish */
 } orc_rule;
+
+static double hermite_he(int n, double x);
+static double factorial(int n);
+
+/* table of He_n(xi_a) / n! for the Grad-Hermite sums */
+static void rule_finish(orc_rule* r)
+{
+    for (int a = 0; a < r->q1; ++a)
+        for (int n = 0; n <= r->order; ++n)
+            r->he[a][n] = hermite_he(n, r->xi[a]) / factorial(n);
+}
 
 /* GH3: roots of He_3 = x^3 - 3x are 0, +-sqrt(3); weights 2/3, 1/6.
  * D2Q9 uses the integer velocities -1, 0, 1 = sqrt(1/3) * (-sqrt3, 0, sqrt3). */
@@ -86,6 +98,7 @@ static void rule_d2q9(orc_rule* r)
     r->w[0] = 1.0 / 6.0;
     r->w[1] = 2.0 / 3.0;
     r->w[2] = 1.0 / 6.0;
+    rule_finish(r);
 }
 
 /* GH5: roots of He_5 = x^5 - 10x^3 + 15x are 0 and x^2 = 5 -+ sqrt(10);
@@ -104,6 +117,7 @@ static void rule_d2q25(orc_rule* r)
     r->xi[3] = xn;  r->w[3] = wn;
     r->xi[4] = xo;  r->w[4] = wo;
     for (int a = 0; a < 5; ++a) r->v[a] = r->xi[a] * sqrt(r->tref);
+    rule_finish(r);
 }
 
 /* probabilists' Hermite polynomial He_n by the three-term recurrence */
@@ -159,8 +173,7 @@ static void grad_hermite_feq(const orc_rule* r, double rho, double ux, double uy
             double sum = 0.0;
             for (int nx = 0; nx <= r->order; ++nx)
                 for (int ny = 0; nx + ny <= r->order; ++ny)
-                    sum += hx[nx] * hy[ny] * hermite_he(nx, r->xi[a]) * hermite_he(ny, r->xi[b])
-                         / (factorial(nx) * factorial(ny));
+                    sum += hx[nx] * hy[ny] * r->he[a][nx] * r->he[b][ny];
             feq[r->q1 * a + b] = r->w[a] * r->w[b] * rho * sum;
         }
 }

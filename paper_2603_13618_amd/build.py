@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblks.so")
-SOURCES = ["lks_api.hip", "common.hip", "d2q9.hip", "d2q9_adjoint.hip"]
+SOURCES = ["lks_api.hip", "common.hip", "d2q9.hip", "d2q9_adjoint.hip", "d2q25.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,418 @@
+// d2q25.hip -- finite-volume step on the 25-velocity Gauss-Hermite lattice
+// (GH5 x GH5, T_ref = 1) for gfx950: van Leer limited upwind fluxes + BGK
+// relaxation toward the order-4 Grad-Hermite equilibrium + sensors S_KL,
+// S_NEQ, S_PI, S_Q + refinement flags + FP64 sums, in one kernel.
+//
+// Method (arXiv 2603.13618): explicit Euler FV update eq. finalDiscretePDE,
+//   f_i^{n+1} = f_i^n - dt/dx sum_faces v_i f_face + dt/tau (f^eq_i - f_i^n),
+// tau = mu/(rho T) (Sec. II.A.2 with p = rho R T, R = 1); the face value is the
+// upwind cell value plus half its van Leer slope, 2ab/(a+b) for same-sign
+// one-sided differences a, b and 0 otherwise (Sec. II.A.3, last paragraph);
+// the equilibrium is the Grad-Hermite expansion to order 4 (Sec. II.A.3),
+// which for a 2D Maxwellian factorises into 1D Hermite coefficients
+// h_n(u, theta) = E[He_n(X)], X ~ N(u, theta); sensors and sums are taken on
+// f^n, the state the collision reads.
+//
+// Layout and staging: SoA planes [25][ny][nx] of deviations d_i = f_i - w_i rho0
+// (the constant part cancels in every flux difference).  A TX x TY workgroup
+// tile stages all 25 planes of its cells plus a two-cell cross-shaped halo in
+// LDS once, then every stencil read comes from LDS.  Tiles are assigned to
+// workgroups so that the eight XCDs each sweep their own band of tile
+// columns row by row: vertically adjacent tiles run on the same XCD shortly
+// after one another, so halo rows are served by that XCD's L2.
+#include "lks_device.h"
+#include "lks_internal.h"
+
+namespace lks {
+
+// GH5 nodes (x-node a, y-node b), He_n(xi)/n! and 1D weights, T_ref = 1
+__device__ __forceinline__ constexpr double gh5_xi(int a)
+{
+    return a == 0 ? -2.856970013872805654 : a == 1 ? -1.355626179974265866 : a == 2 ? 0.0
+         : a == 3 ? 1.355626179974265866 : 2.856970013872805654;
+}
+__device__ __forceinline__ constexpr double gh5_w(int a)
+{
+    return (a == 0 || a == 4) ? 0.011257411327720688933 : (a == 1 || a == 3) ? 0.22207592200561264440
+         : 0.53333333333333333333;
+}
+// He_n(xi_a) / n!, n = 1..4
+__device__ __forceinline__ constexpr double gh5_he(int a, int n)
+{
+    const double s = (a < 2) ? -1.0 : 1.0;
+    if (a == 2) return n == 2 ? -0.5 : (n == 4 ? 0.125 : 0.0);
+    const bool outer = (a == 0 || a == 4);
+    switch (n) {
+    case 1: return s * (outer ? 2.856970013872805654 : 1.355626179974265866);
+    case 2: return outer ? 3.581138830084189666 : 0.4188611699158103340;
+    case 3: return s * (outer ? 2.458078746397754902 : -0.2626023374205813369);
+    default: return outer ? 0.8603796100280632220 : -0.1937129433613965553;
+    }
+}
+
+template <int N, typename F, int I = 0>
+__device__ __forceinline__ void sfor25(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        sfor25<N, F, I + 1>(static_cast<F&&>(f));
+    }
+}
+
+__device__ __forceinline__ int ghost_index(int j, int n, int bc)
+{
+    if (bc == 0) {
+        j %= n;
+        return j < 0 ? j + n : j;
+    }
+    return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+// Hermite coefficients h_1..h_4 of N(u, 1 + tm1) (h_0 = 1)
+template <typename R>
+__device__ __forceinline__ void hermite_h(R u, R tm1, R (&h)[5])
+{
+    const R u2 = u * u;
+    h[0] = R(1);
+    h[1] = u;
+    h[2] = u2 + tm1;
+    h[3] = u * (u2 + R(3) * tm1);
+    h[4] = u2 * (u2 + R(6) * tm1) + R(3) * tm1 * tm1;
+}
+
+// f^eq_i - w_i rho0 for all 25 populations from (rho - rho0, rho, u, theta - 1),
+// with the leading "1" of the expansion taken out so nothing cancels:
+// f^eq_ab = w_a w_b rho (1 + Px~_a + sum_nx Px_a[nx] Sy~_b[4 - nx]).
+template <typename R, typename F>
+__device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& use)
+{
+    R hx[5], hy[5];
+    hermite_h(ux, tm1, hx);
+    hermite_h(uy, tm1, hy);
+    R sy[5][5];           // Sy~_b[m] = sum_{n=1..m} hy[n] He_n(xi_b)/n!
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        sy[b][0] = R(0);
+#pragma unroll
+        for (int m = 1; m < 5; ++m) sy[b][m] = sy[b][m - 1] + hy[m] * R(gh5_he(b, m));
+    }
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        R px[5];
+        R pt = R(0);
+        px[0] = R(1);
+#pragma unroll
+        for (int n = 1; n < 5; ++n) {
+            px[n] = hx[n] * R(gh5_he(a, n));
+            pt += px[n];
+        }
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            R s = pt + sy[b][4];
+#pragma unroll
+            for (int n = 1; n < 4; ++n) s += px[n] * sy[b][4 - n];
+            use(a, b, R(gh5_w(a) * gh5_w(b)) * (rho * s + drho));
+        }
+    }
+}
+
+// half van Leer slope ab/(a+b) for same-sign a, b, else 0
+template <typename R>
+__device__ __forceinline__ R vl_half(R a, R b)
+{
+    const R p = a * b;
+    return p > R(0) ? p * rcp(a + b) : R(0);
+}
+
+// v * (f_face(j + 1/2) - f_face(j - 1/2)) for the stencil q[-2..2] (q[2] = cell j)
+template <typename R, int SIGN>
+__device__ __forceinline__ R flux_diff(R qm2, R qm1, R q0, R qp1, R qp2)
+{
+    if constexpr (SIGN > 0) {
+        const R fr = q0 + vl_half(q0 - qm1, qp1 - q0);
+        const R fl = qm1 + vl_half(qm1 - qm2, q0 - qm1);
+        return fr - fl;
+    } else {
+        const R fr = qp1 - vl_half(qp1 - q0, qp2 - qp1);
+        const R fl = q0 - vl_half(q0 - qm1, qp1 - q0);
+        return fr - fl;
+    }
+}
+
+template <int TX, int TY> struct Tile {
+    static constexpr int kPlane = 4 * TX + TY * (TX + 4);
+    // LDS offset of row r (-2 .. TY+1) at column 0 (columns -2..TX+1 on
+    // interior rows, 0..TX-1 on halo rows)
+    __device__ static int rowbase(int r)
+    {
+        return r < 0 ? (r + 2) * TX : (r < TY ? 2 * TX + r * (TX + 4) + 2 : 2 * TX + TY * (TX + 4) + (r - TY) * TX);
+    }
+};
+
+template <int NW>
+__device__ __forceinline__ void block_sums_n(double (&acc)[kNsums], double* __restrict__ out)
+{
+    __shared__ double red[NW][kNsums];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kNsums; ++k) red[wave][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kNsums) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <typename S, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typename Store<S>::raw* __restrict__ fin,
+                                                   typename Store<S>::raw* __restrict__ fout,
+                                                   typename Store<S>::real* __restrict__ sens,
+                                                   uint8_t* __restrict__ flags,
+                                                   double* __restrict__ partials,
+                                                   unsigned long long* __restrict__ faults)
+{
+    using R = typename Store<S>::real;
+    using T = Tile<TX, TY>;
+    constexpr int NT = TX * TY;
+    __shared__ R lds[25 * T::kPlane];
+
+    const int nx = a.nx, ny = a.ny;
+    const long long plane = a.plane;
+    // XCD-aware tile order: XCD k (= block id mod 8) sweeps column band k
+    int tile_x, tile_y;
+    {
+        const int b = blockIdx.x;
+        if (a.tiles_x % 8 == 0) {
+            const int bw = a.tiles_x / 8, l = b / 8;
+            tile_x = (b % 8) * bw + l % bw;
+            tile_y = l / bw;
+        } else {
+            tile_x = b % a.tiles_x;
+            tile_y = b / a.tiles_x;
+        }
+    }
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int X0 = tile_x * TX, Y0 = tile_y * TY;
+    const int X = X0 + tx, Y = Y0 + ty;
+    const bool active = X < nx && Y < ny;
+    const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
+
+    // ---- stage 25 planes (cells + cross halo) and accumulate the moments
+    const R rho0 = R(a.rho0);
+    R drho = R(0), jx = R(0), jy = R(0), edev = R(0);
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ia = i / 5, ib = i % 5;
+        const typename Store<S>::raw* src = fin + i * plane;
+        R* dst = lds + i * T::kPlane;
+        const R v = Store<S>::to_real(src[(long long)gyc * nx + gxc]);
+        dst[T::rowbase(ty) + tx] = v;
+        drho += v;
+        if constexpr (ia != 2) jx += R(gh5_xi(ia)) * v;
+        if constexpr (ib != 2) jy += R(gh5_xi(ib)) * v;
+        edev += R(0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))) * v;
+        // halo rows -2, -1, TY, TY+1 (columns 0..TX-1)
+        for (int h = threadIdx.x; h < 4 * TX; h += NT) {
+            const int hr = h / TX, c = h % TX;
+            const int r = hr < 2 ? hr - 2 : TY + hr - 2;
+            const int gy = ghost_index(Y0 + r, ny, a.bc_y), gx = ghost_index(X0 + c, nx, a.bc_x);
+            dst[T::rowbase(r) + c] = Store<S>::to_real(src[(long long)gy * nx + gx]);
+        }
+        // halo columns -2, -1, TX, TX+1 (rows 0..TY-1)
+        for (int h = threadIdx.x; h < 4 * TY; h += NT) {
+            const int hc = h % 4, r = h / 4;
+            const int c = hc < 2 ? hc - 2 : TX + hc - 2;
+            const int gy = ghost_index(Y0 + r, ny, a.bc_y), gx = ghost_index(X0 + c, nx, a.bc_x);
+            dst[T::rowbase(r) + c] = Store<S>::to_real(src[(long long)gy * nx + gx]);
+        }
+    });
+    __syncthreads();
+
+    // ---- cell state: rho, u, theta - 1, relaxation factor
+    const R rho = rho0 + drho;
+    const R irho = R(1) / rho;
+    const R ux = jx * irho, uy = jy * irho;
+    // T = (2E/rho - |u|^2)/2 with E = rho0 + edev (sum_i w_i |v_i|^2/2 = 1)
+    const R tm1 = (edev - drho) * irho - R(0.5) * (ux * ux + uy * uy);
+    const R A = R(a.dt / a.dx);
+    const R B = R(a.dt) * rho * (R(1) + tm1) / R(a.mu);   // dt / tau
+
+    const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
+                       T::rowbase(ty + 2)};
+    R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0), qy = R(0);
+    R xmin = R(0), feqmin = R(0);
+    bool first = true;
+    const long long off = (long long)Y * nx + X;
+    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+        const int i = 5 * ia + ib;
+        const R* t = lds + i * T::kPlane;
+        const R d = t[rb[2] + tx];
+        const R fneq = d - deq;
+        const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
+        const R x = fneq * rcp(feq);
+        kl += feq * kl_phi(x);
+        xmin = first ? x : fmin(xmin, x);
+        feqmin = first ? feq : fmin(feqmin, feq);
+        first = false;
+        neq += fabs(fneq);
+        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+        pxx += vx * vx * fneq;
+        pxy += vx * vy * fneq;
+        pyy += vy * vy * fneq;
+        const R e = R(0.5) * (vx * vx + vy * vy);
+        qx += vx * e * fneq;
+        qy += vy * e * fneq;
+        // flux divergence (dimension by dimension, upwind + van Leer)
+        R div = R(0);
+        if (ia != 2) {
+            const R* row = t + rb[2] + tx;
+            div += vx * (ia > 2 ? flux_diff<R, 1>(row[-2], row[-1], d, row[1], R(0))
+                                : flux_diff<R, -1>(R(0), row[-1], d, row[1], row[2]));
+        }
+        if (ib != 2) {
+            div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
+                                : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
+        }
+        if (active) fout[i * plane + off] = Store<S>::from_real(d - A * div + B * (deq - d));
+    });
+
+    const bool fault = !(feqmin > R(0)) || !(xmin > R(-1)) || !(kl == kl);
+    const R s_kl = fault ? R(INFINITY) : kl;
+    const R s_pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+    const R s_q = sqrt(qx * qx + qy * qy);
+    double acc[kNsums];
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
+    if (active) {
+        const R sv[4] = {s_kl, neq, s_pi, s_q};
+        int level = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (a.mask & (1u << s)) {
+                const int l = (sv[s] > R(a.thr[s][0])) + (sv[s] > R(a.thr[s][1]));
+                level = l > level ? l : level;
+            }
+        }
+        sens[off] = s_kl;
+        sens[plane + off] = neq;
+        sens[2 * plane + off] = s_pi;
+        sens[3 * plane + off] = s_q;
+        flags[off] = fault ? uint8_t(0x82) : uint8_t(level);
+        if (fault) atomicAdd(faults, 1ull);
+        acc[0] = (double)drho;
+        acc[1] = (double)jx;
+        acc[2] = (double)jy;
+        acc[3] = (double)edev;
+        acc[4] = (double)s_kl;
+        acc[5] = (double)neq;
+        acc[6] = (double)s_pi;
+        acc[7] = (double)s_q;
+    }
+    block_sums_n<NT / kWave>(acc, partials + (long long)blockIdx.x * kNsums);
+}
+
+template <typename S, int TX, int TY>
+static hipError_t launch_tile(const D2Q25Args& a, const void* fin, void* fout, void* sens, uint8_t* flags,
+                              double* partials, unsigned long long* faults, hipStream_t s)
+{
+    using raw = typename Store<S>::raw;
+    using R = typename Store<S>::real;
+    if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
+    d2q25_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+        a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    return hipGetLastError();
+}
+
+hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fout, void* sens,
+                        uint8_t* flags, double* partials, unsigned long long* faults, hipStream_t s)
+{
+    switch (dtype) {
+    case 0: return launch_tile<double, 32, 2>(a, fin, fout, sens, flags, partials, faults, s);
+    case 1: return launch_tile<float, 64, 4>(a, fin, fout, sens, flags, partials, faults, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// tile shape the launcher expects for a storage type
+void d2q25_tile_shape(int dtype, int* tx, int* ty)
+{
+    *tx = dtype == 0 ? 32 : 64;
+    *ty = dtype == 0 ? 2 : 4;
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium initialiser and moment readout (one thread per cell, FP64 math)
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(kBlock) void d2q25_init_kernel(long long n, double rho0, const double* __restrict__ rho,
+                                                       const double* __restrict__ ux,
+                                                       const double* __restrict__ uy,
+                                                       const double* __restrict__ T,
+                                                       typename Store<S>::raw* __restrict__ pop)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    const double r = rho[c];
+    d2q25_deq<double>(r - rho0, r, ux[c], uy[c], T[c] - 1.0, [&](int ia, int ib, double deq) {
+        pop[(5 * ia + ib) * n + c] = Store<S>::from_real((typename Store<S>::real)deq);
+    });
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void d2q25_moments_kernel(long long n, double rho0,
+                                                          const typename Store<S>::raw* __restrict__ pop,
+                                                          double* __restrict__ rho, double* __restrict__ ux,
+                                                          double* __restrict__ uy, double* __restrict__ T)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    double drho = 0.0, jx = 0.0, jy = 0.0, edev = 0.0;
+#pragma unroll
+    for (int i = 0; i < 25; ++i) {
+        const double d = (double)Store<S>::to_real(pop[i * n + c]);
+        const double vx = gh5_xi(i / 5), vy = gh5_xi(i % 5);
+        drho += d;
+        jx += vx * d;
+        jy += vy * d;
+        edev += 0.5 * (vx * vx + vy * vy) * d;
+    }
+    const double r = rho0 + drho;
+    const double u = jx / r, v = jy / r;
+    rho[c] = r;
+    ux[c] = u;
+    uy[c] = v;
+    if (T) T[c] = 1.0 + (edev - drho) / r - 0.5 * (u * u + v * v);
+}
+
+hipError_t launch_d2q25_init(int dtype, long long n, double rho0, const double* rho, const double* ux,
+                             const double* uy, const double* T, void* pop, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    switch (dtype) {
+    case 0: d2q25_init_kernel<double><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, T, (double*)pop); break;
+    case 1: d2q25_init_kernel<float><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, T, (float*)pop); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_d2q25_moments(int dtype, long long n, double rho0, const void* pop, double* rho,
+                                double* ux, double* uy, double* T, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    switch (dtype) {
+    case 0: d2q25_moments_kernel<double><<<grid, block, 0, s>>>(n, rho0, (const double*)pop, rho, ux, uy, T); break;
+    case 1: d2q25_moments_kernel<float><<<grid, block, 0, s>>>(n, rho0, (const float*)pop, rho, ux, uy, T); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+} // namespace lks

@@ -77,12 +77,48 @@ const char* validate_config(const lks_config* c)
     return nullptr;
 }
 
+lks::D2Q25Args d2q25_args(const lks_config& c)
+{
+    lks::D2Q25Args a;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.plane = (long long)c.nx * c.ny;
+    a.bc_x = c.bc_x;
+    a.bc_y = c.bc_y;
+    a.mu = c.mu;
+    a.dt = c.dt;
+    a.dx = c.dx;
+    a.rho0 = c.rho0;
+    std::memcpy(a.thr, c.thr, sizeof(a.thr));
+    a.mask = c.flag_mask;
+    lks::d2q25_tile_shape(c.dtype, &a.tile_x, &a.tile_y);
+    a.tiles_x = (c.nx + a.tile_x - 1) / a.tile_x;
+    a.tiles_y = (c.ny + a.tile_y - 1) / a.tile_y;
+    a.nblocks = a.tiles_x * a.tiles_y;
+    return a;
+}
+
+// workgroups of one step's cell kernel (the most any launch shape uses)
+int step_blocks(const lks_config& c)
+{
+    if (c.lattice == LKS_D2Q25) return d2q25_args(c).nblocks;
+    return d2q9_shape(c, 1).nblocks;   // the narrowest vector has the most workgroups
+}
+
+// steps whose partial sums share the scratch before one reduction launch
+int chunk_steps(const lks_config& c)
+{
+    const long long per_step = (long long)step_blocks(c) * lks::kNsumsHost * sizeof(double);
+    long long k = (16LL << 20) / (per_step > 0 ? per_step : 1);
+    if (k < 1) k = 1;
+    if (k > kMaxChunk) k = kMaxChunk;
+    if (k > c.max_steps) k = c.max_steps;
+    return (int)k;
+}
+
 size_t scratch_for(const lks_config& c)
 {
-    // sized for the narrowest vector width, which has the most workgroups
-    const lks::GridShape g = d2q9_shape(c, 1);
-    const int chunk = c.max_steps < kMaxChunk ? c.max_steps : kMaxChunk;
-    return kHeader + (size_t)chunk * (size_t)g.nblocks * lks::kNsumsHost * sizeof(double);
+    return kHeader + (size_t)chunk_steps(c) * (size_t)step_blocks(c) * lks::kNsumsHost * sizeof(double);
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -100,6 +136,8 @@ struct lks_ctx {
     bool ready;
     int chunk;
     lks::D2Q9Args a9;
+    lks::D2Q25Args a25;
+    int nblocks;
     double* partials;
     unsigned long long* faults;
     std::string err;
@@ -138,8 +176,8 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     *out = nullptr;
     if (const char* m = validate_config(cfg)) return fail(nullptr, LKS_EINVAL, m);
     if (!buf) return fail(nullptr, LKS_EINVAL, "buffers are NULL");
-    if (cfg->lattice == LKS_D2Q25)
-        return fail(nullptr, LKS_EUNSUPPORTED, "D2Q25 is not available in this build");
+    if (cfg->lattice == LKS_D2Q25 && cfg->dtype != LKS_F32 && cfg->dtype != LKS_F64)
+        return fail(nullptr, LKS_EUNSUPPORTED, "D2Q25 supports F32 and F64 storage");
     if (!buf->pop[0] || !buf->pop[1] || !buf->sensors || !buf->flags || !buf->sums || !buf->scratch)
         return fail(nullptr, LKS_EINVAL, "a buffer pointer is NULL");
     if (buf->pop[0] == buf->pop[1]) return fail(nullptr, LKS_EINVAL, "pop[0] and pop[1] alias");
@@ -165,7 +203,7 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     c->cur = 0;
     c->steps = 0;
     c->ready = false;
-    c->chunk = cfg->max_steps < kMaxChunk ? cfg->max_steps : kMaxChunk;
+    c->chunk = chunk_steps(*cfg);
     c->faults = reinterpret_cast<unsigned long long*>(buf->scratch);
     c->partials = reinterpret_cast<double*>(static_cast<char*>(buf->scratch) + kHeader);
 
@@ -184,6 +222,8 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     std::memcpy(a.thr, cfg->thr, sizeof(a.thr));
     a.mask = cfg->flag_mask;
     a.g = d2q9_shape(*cfg, vec);
+    c->a25 = d2q25_args(*cfg);
+    c->nblocks = cfg->lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
     *out = c;
     return LKS_OK;
 }
@@ -194,8 +234,11 @@ lks_status lks_init_equilibrium(lks_ctx* c, const double* rho, const double* ux,
     if (!c) return LKS_EINVAL;
     if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
     if (c->cfg.lattice == LKS_D2Q25 && !T) return fail(c, LKS_EINVAL, "T is required on D2Q25");
-    hipError_t e = lks::launch_d2q9_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy,
-                                         c->buf.pop[0], c->stream);
+    hipError_t e = c->cfg.lattice == LKS_D2Q25
+                       ? lks::launch_d2q25_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy, T,
+                                                c->buf.pop[0], c->stream)
+                       : lks::launch_d2q9_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy,
+                                               c->buf.pop[0], c->stream);
     if (lks_status s = hip_check(c, e, "init kernel")) return s;
     if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
     c->cur = 0;
@@ -222,8 +265,10 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
     if (nsteps < 0) return fail(c, LKS_EINVAL, "nsteps must be >= 0");
     if (fused != 0 && fused != 1) return fail(c, LKS_EINVAL, "fused must be 0 or 1");
     if (!c->ready) return fail(c, LKS_ESTATE, "step before init_equilibrium or restore");
+    const bool q25 = c->cfg.lattice == LKS_D2Q25;
+    if (q25 && !fused) return fail(c, LKS_EUNSUPPORTED, "the unfused passes exist for D2Q9 only");
     const lks::D2Q9Args& a = c->a9;
-    const int nb = a.g.nblocks;
+    const int nb = c->nblocks;
     int done = 0;
     while (done < nsteps) {
         const int m = (nsteps - done) < c->chunk ? (nsteps - done) : c->chunk;
@@ -232,7 +277,11 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
             void* f = c->buf.pop[c->cur];
             void* g = c->buf.pop[1 - c->cur];
             hipError_t e;
-            if (fused) {
+            if (q25) {
+                e = lks::launch_d2q25(c->cfg.dtype, c->a25, f, g, c->buf.sensors, c->buf.flags, part,
+                                      c->faults, c->stream);
+                if (e == hipSuccess) c->cur = 1 - c->cur;
+            } else if (fused) {
                 e = lks::launch_d2q9(c->cfg.dtype, lks::kFused, a, f, g, c->buf.sensors,
                                      c->buf.flags, part, c->faults, c->stream);
                 if (e == hipSuccess) c->cur = 1 - c->cur;
@@ -249,8 +298,9 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
             if (lks_status st = hip_check(c, e, "step kernel")) return st;
         }
         const double mass_ref = (double)c->n * c->cfg.rho0;
+        const double energy_ref = q25 ? mass_ref : 0.0;   // sum_i w_i |v_i|^2 / 2 = 1 on D2Q25
         hipError_t e = lks::launch_finalize(c->partials, nb, m, c->buf.sums, c->steps,
-                                            c->cfg.max_steps, mass_ref, 0.0, c->stream);
+                                            c->cfg.max_steps, mass_ref, energy_ref, c->stream);
         if (lks_status st = hip_check(c, e, "finalize kernel")) return st;
         c->steps += m;
         done += m;
@@ -271,8 +321,11 @@ lks_status lks_moments(lks_ctx* c, double* rho, double* ux, double* uy, double* 
     if (!c) return LKS_EINVAL;
     if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
     if (!c->ready) return fail(c, LKS_ESTATE, "moments before init_equilibrium or restore");
-    hipError_t e = lks::launch_d2q9_moments(c->cfg.dtype, c->n, c->cfg.rho0, c->buf.pop[c->cur],
-                                            rho, ux, uy, T, c->stream);
+    hipError_t e = c->cfg.lattice == LKS_D2Q25
+                       ? lks::launch_d2q25_moments(c->cfg.dtype, c->n, c->cfg.rho0,
+                                                   c->buf.pop[c->cur], rho, ux, uy, T, c->stream)
+                       : lks::launch_d2q9_moments(c->cfg.dtype, c->n, c->cfg.rho0,
+                                                  c->buf.pop[c->cur], rho, ux, uy, T, c->stream);
     return hip_check(c, e, "moments kernel");
 }
 
@@ -325,8 +378,12 @@ lks_status lks_step_from(lks_ctx* c, const void* src, void* dst)
     if (!c) return LKS_EINVAL;
     if (!src || !dst) return fail(c, LKS_EINVAL, "src and dst are required");
     if (src == dst) return fail(c, LKS_EINVAL, "src and dst must differ");
-    hipError_t e = lks::launch_d2q9(c->cfg.dtype, lks::kFused, c->a9, src, dst, c->buf.sensors,
-                                    c->buf.flags, c->partials, c->faults, c->stream);
+    hipError_t e = c->cfg.lattice == LKS_D2Q25
+                       ? lks::launch_d2q25(c->cfg.dtype, c->a25, src, dst, c->buf.sensors,
+                                           c->buf.flags, c->partials, c->faults, c->stream)
+                       : lks::launch_d2q9(c->cfg.dtype, lks::kFused, c->a9, src, dst,
+                                          c->buf.sensors, c->buf.flags, c->partials, c->faults,
+                                          c->stream);
     return hip_check(c, e, "step kernel");
 }
 

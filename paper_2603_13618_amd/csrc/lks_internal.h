@@ -53,6 +53,8 @@ hipError_t launch_d2q9(int dtype, int pass, const D2Q9Args& a, const void* fin, 
 hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fout, void* sens,
                         uint8_t* flags, double* partials, unsigned long long* faults,
                         hipStream_t s);
+// workgroup tile (cells) of the D2Q25 kernel for a storage type
+void d2q25_tile_shape(int dtype, int* tx, int* ty);
 
 // equilibrium initial states from FP64 fields [ny][nx] (n = nx*ny cells)
 hipError_t launch_d2q9_init(int dtype, long long n, double rho0, const double* rho,

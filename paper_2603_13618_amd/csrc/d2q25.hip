@@ -204,34 +204,59 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
     const bool active = X < nx && Y < ny;
     const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
 
-    // ---- stage 25 planes (cells + cross halo) and accumulate the moments
+    // ---- global offsets of this thread's staging loads (the same for every
+    //      population plane): its own cell, up to HR halo-row cells and one
+    //      halo-column cell
+    constexpr int HR = (4 * TX + NT - 1) / NT;
+    long long own = (long long)gyc * nx + gxc;
+    long long hoff[HR];
+    int hlds[HR];
+#pragma unroll
+    for (int k = 0; k < HR; ++k) {
+        const int h = threadIdx.x + k * NT;
+        const int hr = h / TX, c = h % TX;
+        const int r = hr < 2 ? hr - 2 : TY + hr - 2;
+        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
+    }
+    long long coff = 0;
+    int clds = -1;
+    if (threadIdx.x < 4 * TY) {
+        const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
+        const int c = hc < 2 ? hc - 2 : TX + hc - 2;
+        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        clds = T::rowbase(r) + c;
+    }
+    const int olds = T::rowbase(ty) + tx;
+
+    // ---- stage 25 planes (cells + cross halo) and accumulate the moments.
+    //      All loads are issued before the first LDS write so that the 25
+    //      planes' latencies overlap instead of adding up.
     const R rho0 = R(a.rho0);
+    R vin[25], vh[HR][25], vc[25];
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const typename Store<S>::raw* src = fin + i * plane;
+        vin[i] = Store<S>::to_real(src[own]);
+#pragma unroll
+        for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
+        vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
+    });
     R drho = R(0), jx = R(0), jy = R(0), edev = R(0);
     sfor25<25>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ia = i / 5, ib = i % 5;
-        const typename Store<S>::raw* src = fin + i * plane;
         R* dst = lds + i * T::kPlane;
-        const R v = Store<S>::to_real(src[(long long)gyc * nx + gxc]);
-        dst[T::rowbase(ty) + tx] = v;
+        const R v = vin[i];
+        dst[olds] = v;
         drho += v;
         if constexpr (ia != 2) jx += R(gh5_xi(ia)) * v;
         if constexpr (ib != 2) jy += R(gh5_xi(ib)) * v;
         edev += R(0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))) * v;
-        // halo rows -2, -1, TY, TY+1 (columns 0..TX-1)
-        for (int h = threadIdx.x; h < 4 * TX; h += NT) {
-            const int hr = h / TX, c = h % TX;
-            const int r = hr < 2 ? hr - 2 : TY + hr - 2;
-            const int gy = ghost_index(Y0 + r, ny, a.bc_y), gx = ghost_index(X0 + c, nx, a.bc_x);
-            dst[T::rowbase(r) + c] = Store<S>::to_real(src[(long long)gy * nx + gx]);
-        }
-        // halo columns -2, -1, TX, TX+1 (rows 0..TY-1)
-        for (int h = threadIdx.x; h < 4 * TY; h += NT) {
-            const int hc = h % 4, r = h / 4;
-            const int c = hc < 2 ? hc - 2 : TX + hc - 2;
-            const int gy = ghost_index(Y0 + r, ny, a.bc_y), gx = ghost_index(X0 + c, nx, a.bc_x);
-            dst[T::rowbase(r) + c] = Store<S>::to_real(src[(long long)gy * nx + gx]);
-        }
+#pragma unroll
+        for (int k = 0; k < HR; ++k)
+            if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];
+        if (clds >= 0) dst[clds] = vc[i];
     });
     __syncthreads();
 
@@ -247,7 +272,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
     const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
                        T::rowbase(ty + 2)};
     R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0), qy = R(0);
-    R xmin = R(0), feqmin = R(0);
+    R xmin = R(0), xmax = R(0), feqmin = R(0);
     bool first = true;
     const long long off = (long long)Y * nx + X;
     d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
@@ -257,8 +282,9 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
         const R fneq = d - deq;
         const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
         const R x = fneq * rcp(feq);
-        kl += feq * kl_phi(x);
+        kl += (fneq * x) * kl_series(x);           // series branch; fallback below
         xmin = first ? x : fmin(xmin, x);
+        xmax = first ? fabs(x) : fmax(xmax, fabs(x));
         feqmin = first ? feq : fmin(feqmin, feq);
         first = false;
         neq += fabs(fneq);
@@ -282,6 +308,15 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
         }
         if (active) fout[i * plane + off] = Store<S>::from_real(d - A * div + B * (deq - d));
     });
+    if (!(xmax <= KlCut<R>::v)) {
+        // rare: some population far from equilibrium (or NaN): the closed form
+        kl = R(0);
+        d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+            const R d = lds[(5 * ia + ib) * T::kPlane + rb[2] + tx];
+            const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
+            kl += feq * kl_phi((d - deq) * rcp(feq));
+        });
+    }
 
     const bool fault = !(feqmin > R(0)) || !(xmin > R(-1)) || !(kl == kl);
     const R s_kl = fault ? R(INFINITY) : kl;

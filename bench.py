@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--forms", action="store_true",
                    help="also time the BF16/FP16 storage forms on the 8192^2 workload")
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
+    p.add_argument("--workload", choices=["smooth4096", "riemann2048", "smooth8192-bf16",
+                                          "smooth8192-f16", "adjoint1024"],
+                   default="smooth4096", help="workload of --mode kernel (profiling runs)")
     p.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                    help="assemble the traffic summary from four rocprofv3 --pmc output "
                         "directories (FETCH_SIZE and WRITE_SIZE of '--mode kernel', then of "
@@ -173,6 +176,10 @@ def main():
     lat.init(rho, ux, uy)
 
     if args.mode == "kernel":
+        if args.workload != "smooth4096":
+            del lat
+            kernel_only(args, torch, lks, inputs, workloads, dev)
+            return
         lat.step(args.steps)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "kernel", "steps": args.steps}))
@@ -266,6 +273,40 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def kernel_only(args, torch, lks, inputs, workloads, dev):
+    """A short run of one of the other workloads (for profilers)."""
+    if args.workload == "riemann2048":
+        wl = workloads.RIEMANN_2048
+        n = wl["nx"]
+        rho, ux, uy, T, states = inputs.riemann_quadrants(n, seed=wl["seed"])
+        dx = 1.0 / n
+        lat = lks.Lattice(25, n, n, "f32", mu=wl["mu"], dt=inputs.riemann_dt(states, dx), dx=dx,
+                          bc=(1, 1), thr=wl["thr"], flag_mask=wl["flag_mask"],
+                          max_steps=max(args.steps, 1), device=dev)
+        lat.init(rho, ux, uy, T)
+        lat.step(args.steps)
+    elif args.workload.startswith("smooth8192"):
+        wl = workloads.SMOOTH_8192
+        n = wl["nx"]
+        rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+        lat = lks.Lattice(9, n, n, args.workload.split("-")[1], tau=wl["tau"], thr=wl["thr"],
+                          flag_mask=wl["flag_mask"], max_steps=max(args.steps, 1), device=dev)
+        lat.init(rho, ux, uy)
+        lat.step(args.steps)
+    else:
+        from paper_2603_13618_amd import adjoint
+        wl = workloads.ADJOINT_1024
+        n = wl["nx"]
+        rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+        u = torch.tensor(ux, device=dev, requires_grad=True)
+        v = torch.tensor(uy, device=dev, requires_grad=True)
+        L = adjoint.kl_sensor_loss(u, v, torch.tensor(rho, device=dev), tau=wl["tau"],
+                                   nsteps=args.steps, checkpoint=wl["checkpoint"], dtype="f32")
+        L.backward()
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernel", "workload": args.workload, "steps": args.steps}))
 
 
 def time_forms(torch, lks, inputs, workloads, dev, ev):

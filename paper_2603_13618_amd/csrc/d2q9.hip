@@ -122,14 +122,11 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
     if constexpr (SENSE) {
         R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
         R xmax = R(0), xmin = R(0), feqmin = R(0);
-        R xs[9], fe[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const R fneq = d[i] - deq[i];
             const R feq = w9<R>(i) * rho0 + deq[i];
             const R x = fneq * rcp(feq);
-            xs[i] = x;
-            fe[i] = feq;
             // S_KL term feq phi(x) = fneq x p(x) on the series branch
             kl += (fneq * x) * kl_series(x);
             xmax = i == 0 ? fabs(x) : fmax(xmax, fabs(x));
@@ -139,18 +136,21 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
             if (cx9(i) != 0) pxx += fneq;
             if (cy9(i) != 0) pyy += fneq;
             if (cx9(i) * cy9(i) != 0) pxy += R(cx9(i) * cy9(i)) * fneq;
-            if constexpr (COLLIDE) d[i] -= inv_tau * fneq;
         }
         if (!(xmax <= KlCut<R>::v)) {       // rare: far from equilibrium (or NaN)
             kl = R(0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) kl += fe[i] * kl_phi(xs[i]);
+            for (int i = 0; i < 9; ++i) {
+                const R feq = w9<R>(i) * rho0 + deq[i];
+                kl += feq * kl_phi((d[i] - deq[i]) * rcp(feq));
+            }
         }
         out.fault = !(feqmin > R(0)) || !(xmin > R(-1)) || !(kl == kl);
         out.kl = out.fault ? R(INFINITY) : kl;
         out.neq = neq;
         out.pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
-    } else if constexpr (COLLIDE) {
+    }
+    if constexpr (COLLIDE) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) d[i] -= inv_tau * (d[i] - deq[i]);
     }

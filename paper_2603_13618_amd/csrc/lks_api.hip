@@ -32,8 +32,9 @@ lks::GridShape d2q9_shape(const lks_config& c, int vec)
     g.tiles_x = (c.nx + kBlock * vec - 1) / (kBlock * vec);
     int rows = c.launch_rows;
     if (rows <= 0) {
-        // aim at ~4096 workgroups (16 per CU) so partial sums stay small
-        const long long target = 4096;
+        // ~1024 workgroups (4 per CU): long row sweeps keep the one-row
+        // prefetch busy and the partial sums small
+        const long long target = 1024;
         long long r = ((long long)g.tiles_x * c.ny) / target;
         rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
     }

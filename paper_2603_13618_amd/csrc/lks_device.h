@@ -22,6 +22,10 @@
 #ifndef LKS_NT_STORES
 #define LKS_NT_STORES 0
 #endif
+// Non-temporal loads for the population planes (read once per step).
+#ifndef LKS_NT_LOADS
+#define LKS_NT_LOADS 0
+#endif
 
 namespace lks {
 
@@ -109,7 +113,21 @@ __device__ __forceinline__ void load_vec(const typename Store<S>::raw* __restric
                                          typename Store<S>::real (&out)[VEC])
 {
     using raw = typename Store<S>::raw;
+#if LKS_NT_LOADS
+    constexpr int bytes = (int)sizeof(raw) * VEC;
+    Pack<raw, VEC> pk;
+    if constexpr (bytes == 16) {
+        using V = __attribute__((ext_vector_type(4))) unsigned int;
+        pk = __builtin_bit_cast(Pack<raw, VEC>, __builtin_nontemporal_load(reinterpret_cast<const V*>(p)));
+    } else if constexpr (bytes == 8) {
+        using V = __attribute__((ext_vector_type(2))) unsigned int;
+        pk = __builtin_bit_cast(Pack<raw, VEC>, __builtin_nontemporal_load(reinterpret_cast<const V*>(p)));
+    } else {
+        pk = *reinterpret_cast<const Pack<raw, VEC>*>(p);
+    }
+#else
     const Pack<raw, VEC> pk = *reinterpret_cast<const Pack<raw, VEC>*>(p);
+#endif
 #pragma unroll
     for (int k = 0; k < VEC; ++k) out[k] = Store<S>::to_real(pk.v[k]);
 }

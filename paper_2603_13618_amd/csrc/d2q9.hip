@@ -203,24 +203,30 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
     const int y0 = rg * a.g.rows;
     const int y1 = min(y0 + a.g.rows, ny);
 
-    const R rho0 = R(a.rho0);
-    const R inv_tau = R(1.0 / a.tau);
+    constexpr bool F32 = sizeof(R) == 4;
+    const R rho0 = F32 ? R(a.rho0_f) : R(a.rho0);
+    const R inv_tau = F32 ? R(a.inv_tau_f) : R(1.0 / a.tau);
     R th[3][2];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        th[s][0] = R(a.thr[s][0]);
-        th[s][1] = R(a.thr[s][1]);
+        th[s][0] = F32 ? R(a.thr_f[s][0]) : R(a.thr[s][0]);
+        th[s][1] = F32 ? R(a.thr_f[s][1]) : R(a.thr[s][1]);
     }
     double acc[kNsums];
 #pragma unroll
     for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
     unsigned nfault = 0;
 
-    R cur[9][VEC];
-    if (y0 < y1) load_row<S, VEC, PULL>(fin, plane, y0, nx, ny, x0, active, lane, cur);
+    // ring of PF + 1 rows: rows y .. y + PF - 1 are loaded or in flight while
+    // row y is computed
+    constexpr int PF = LKS_D2Q9_PREFETCH;
+    R ring[PF + 1][9][VEC];
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+        if (y0 + p < y1) load_row<S, VEC, PULL>(fin, plane, y0 + p, nx, ny, x0, active, lane, ring[p]);
     for (int y = y0; y < y1; ++y) {                 // uniform across the workgroup
-        R nxt[9][VEC];
-        if (y + 1 < y1) load_row<S, VEC, PULL>(fin, plane, y + 1, nx, ny, x0, active, lane, nxt);
+        if (y + PF < y1) load_row<S, VEC, PULL>(fin, plane, y + PF, nx, ny, x0, active, lane, ring[PF]);
+        R (&cur)[9][VEC] = ring[0];
         const long long off = (long long)y * nx + x0;
 
         if constexpr (PASS == kStream) {
@@ -238,6 +244,7 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
 #pragma unroll
                 for (int i = 0; i < 9; ++i) dc[i] = cur[i][k];
                 R drho, jx, jy;
+                LKS_CELL_BARRIER();
                 const CellSense<R> cs = cell_update<R, SENSE, COLLIDE>(dc, rho0, inv_tau, drho, jx, jy);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) cur[i][k] = dc[i];
@@ -288,14 +295,169 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
             }
         }
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
+        for (int p = 0; p < PF; ++p)
 #pragma unroll
-            for (int k = 0; k < VEC; ++k) cur[i][k] = nxt[i][k];
+            for (int i = 0; i < 9; ++i)
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) ring[p][i][k] = ring[p + 1][i][k];
     }
     if constexpr (SENSE) {
         if (nfault) atomicAdd(faults, (unsigned long long)nfault);
         block_sums(acc, partials + (long long)blockIdx.x * kNsums);
     }
+}
+
+// Fused step with the next row staged through LDS by direct global->LDS
+// loads (16 bytes per lane per population): the row in flight costs no
+// registers, so more waves fit per SIMD.  Each wave owns a private 9 x 1 KB
+// staging area; lane l's 16 bytes of population i land at i*1024 + 16*l and
+// are read back by the same lane.
+template <typename S>
+__global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
+    D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
+    typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags,
+    double* __restrict__ partials, unsigned long long* __restrict__ faults)
+{
+    using R = typename Store<S>::real;
+    using raw = typename Store<S>::raw;
+    constexpr int VEC = 16 / (int)sizeof(raw);
+    typedef __attribute__((address_space(1))) void gvoid;
+    typedef __attribute__((address_space(3))) void lvoid;
+    __shared__ __attribute__((aligned(16))) unsigned char stage[kBlock / kWave][9][kWave * 16];
+
+    const int nx = a.nx, ny = a.ny;
+    const long long plane = a.plane;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int tx = blockIdx.x % a.g.tiles_x;
+    const int rg = blockIdx.x / a.g.tiles_x;
+    const int x0 = (tx * kBlock + threadIdx.x) * VEC;
+    const bool active = x0 < nx;
+    const int y0 = rg * a.g.rows;
+    const int y1 = min(y0 + a.g.rows, ny);
+
+    constexpr bool F32 = sizeof(R) == 4;
+    const R rho0 = F32 ? R(a.rho0_f) : R(a.rho0);
+    const R inv_tau = F32 ? R(a.inv_tau_f) : R(1.0 / a.tau);
+    R th[3][2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        th[s][0] = F32 ? R(a.thr_f[s][0]) : R(a.thr[s][0]);
+        th[s][1] = F32 ? R(a.thr_f[s][1]) : R(a.thr[s][1]);
+    }
+    double acc[kNsums];
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
+    unsigned nfault = 0;
+
+    // x-shifted populations also need one value outside the lane's 16 bytes;
+    // only the wave's edge lanes (and the row ends) load it, into registers
+    R edge[9];
+    auto issue = [&](int y) {
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int cx = cx9(i), cy = cy9(i);
+            int ys = y - cy;
+            ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+            const raw* row = fin + i * plane + (long long)ys * nx;
+            if (active)
+                __builtin_amdgcn_global_load_lds((gvoid*)(row + x0), (lvoid*)&stage[wave][i][0], 16, 0, 0);
+            if constexpr (cx == 1) {
+                edge[i] = R(0);
+                if (active && (lane == 0 || x0 == 0))
+                    edge[i] = Store<S>::to_real(row[x0 == 0 ? nx - 1 : x0 - 1]);
+            } else if constexpr (cx == -1) {
+                edge[i] = R(0);
+                if (active && (lane == kWave - 1 || x0 + VEC >= nx))
+                    edge[i] = Store<S>::to_real(row[x0 + VEC >= nx ? 0 : x0 + VEC]);
+            }
+        });
+    };
+
+    if (y0 < y1) issue(y0);
+    for (int y = y0; y < y1; ++y) {                 // uniform across the workgroup
+        R cur[9][VEC];
+        static_for<9>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int cx = cx9(i);
+            R v[VEC];
+            load_vec<S, VEC>(reinterpret_cast<const raw*>(&stage[wave][i][lane * 16]), v);
+            if constexpr (cx == 0) {
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) cur[i][k] = v[k];
+            } else if constexpr (cx == 1) {
+                R prev = __shfl_up(v[VEC - 1], 1, kWave);
+                if (lane == 0 || x0 == 0) prev = edge[i];
+                cur[i][0] = prev;
+#pragma unroll
+                for (int k = 1; k < VEC; ++k) cur[i][k] = v[k - 1];
+            } else {
+                R next = __shfl_down(v[0], 1, kWave);
+                if (lane == kWave - 1 || x0 + VEC >= nx) next = edge[i];
+#pragma unroll
+                for (int k = 0; k + 1 < VEC; ++k) cur[i][k] = v[k + 1];
+                cur[i][VEC - 1] = next;
+            }
+        });
+        // the staging area is rewritten by the next row's loads only after
+        // every lane's reads of this row have completed
+        __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0)
+        if (y + 1 < y1) issue(y + 1);
+        const long long off = (long long)y * nx + x0;
+
+        R s_kl[VEC], s_neq[VEC], s_pi[VEC];
+        uint8_t fl[VEC];
+        R rsum[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            R dc[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dc[i] = cur[i][k];
+            R drho, jx, jy;
+            LKS_CELL_BARRIER();
+            const CellSense<R> cs = cell_update<R, true, true>(dc, rho0, inv_tau, drho, jx, jy);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) cur[i][k] = dc[i];
+            int level = 0;
+            const R sv[3] = {cs.kl, cs.neq, cs.pi};
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                if (a.mask & (1u << s)) {
+                    const int l = (sv[s] > th[s][0]) + (sv[s] > th[s][1]);
+                    level = l > level ? l : level;
+                }
+            }
+            fl[k] = cs.fault ? uint8_t(0x82) : uint8_t(level);
+            s_kl[k] = cs.kl;
+            s_neq[k] = cs.neq;
+            s_pi[k] = cs.pi;
+            if (active) {
+                rsum[0] += drho;
+                rsum[1] += jx;
+                rsum[2] += jy;
+                rsum[3] += cs.kl;
+                rsum[4] += cs.neq;
+                rsum[5] += cs.pi;
+                nfault += cs.fault ? 1u : 0u;
+            }
+        }
+        acc[0] += (double)rsum[0];
+        acc[1] += (double)rsum[1];
+        acc[2] += (double)rsum[2];
+        acc[4] += (double)rsum[3];
+        acc[5] += (double)rsum[4];
+        acc[6] += (double)rsum[5];
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, cur[i]);
+            store_pack<R, VEC>(sens + off, s_kl);
+            store_pack<R, VEC>(sens + plane + off, s_neq);
+            store_pack<R, VEC>(sens + 2 * plane + off, s_pi);
+            store_pack<uint8_t, VEC>(flags + off, fl);
+        }
+    }
+    if (nfault) atomicAdd(faults, (unsigned long long)nfault);
+    block_sums(acc, partials + (long long)blockIdx.x * kNsums);
 }
 
 template <typename S, int VEC>
@@ -311,7 +473,10 @@ static hipError_t launch_pass(int pass, const D2Q9Args& a, const void* fin, void
     const dim3 grid(a.g.nblocks), block(kBlock);
     switch (pass) {
     case kFused:
-        d2q9_kernel<S, VEC, kFused><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        if (LKS_D2Q9_LDS_STAGE && VEC * (int)sizeof(raw) == 16)
+            d2q9_fused_lds<S><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        else
+            d2q9_kernel<S, VEC, kFused><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
         break;
     case kStream:
         d2q9_kernel<S, VEC, kStream><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);

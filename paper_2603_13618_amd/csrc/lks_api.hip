@@ -32,11 +32,12 @@ lks::GridShape d2q9_shape(const lks_config& c, int vec)
     g.tiles_x = (c.nx + kBlock * vec - 1) / (kBlock * vec);
     int rows = c.launch_rows;
     if (rows <= 0) {
-        // ~1024 workgroups (4 per CU): long row sweeps keep the one-row
-        // prefetch busy and the partial sums small
+        // at least ~1024 workgroups (4 per CU) with row sweeps of at most 16
+        // rows: long enough to keep the next row in flight behind the
+        // arithmetic, short enough to balance the CUs
         const long long target = 1024;
         long long r = ((long long)g.tiles_x * c.ny) / target;
-        rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
+        rows = (int)(r < 1 ? 1 : (r > 16 ? 16 : r));
     }
     if (rows > c.ny) rows = c.ny;
     g.rows = rows;
@@ -223,6 +224,10 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     std::memcpy(a.thr, cfg->thr, sizeof(a.thr));
     a.mask = cfg->flag_mask;
     a.g = d2q9_shape(*cfg, vec);
+    a.inv_tau_f = (float)(1.0 / cfg->tau);
+    a.rho0_f = (float)cfg->rho0;
+    for (int s = 0; s < LKS_MAX_SENSORS; ++s)
+        for (int k = 0; k < 2; ++k) a.thr_f[s][k] = (float)cfg->thr[s][k];
     c->a25 = d2q25_args(*cfg);
     c->nblocks = cfg->lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
     *out = c;

@@ -22,6 +22,26 @@
 #ifndef LKS_NT_STORES
 #define LKS_NT_STORES 0
 #endif
+// Rows of populations the D2Q9 kernel keeps in flight ahead of the row it
+// computes.
+#ifndef LKS_D2Q9_PREFETCH
+#define LKS_D2Q9_PREFETCH 1
+#endif
+// 1 = the fused D2Q9 step stages the next row through LDS with direct
+// global->LDS loads where a lane's cells span 16 bytes (FP32 x 4, FP64 x 2).
+#ifndef LKS_D2Q9_LDS_STAGE
+#define LKS_D2Q9_LDS_STAGE 1
+#endif
+// 1 = a scheduling barrier between the cells a thread updates, so the
+// compiler does not interleave them (shorter live ranges, fewer VGPRs).
+#ifndef LKS_CELL_SCHED_BARRIER
+#define LKS_CELL_SCHED_BARRIER 0
+#endif
+#if LKS_CELL_SCHED_BARRIER
+#define LKS_CELL_BARRIER() __builtin_amdgcn_sched_barrier(0)
+#else
+#define LKS_CELL_BARRIER() ((void)0)
+#endif
 // Non-temporal loads for the population planes (read once per step).
 #ifndef LKS_NT_LOADS
 #define LKS_NT_LOADS 0

@@ -27,6 +27,10 @@ struct D2Q9Args {
     double thr[4][2];
     unsigned mask;
     GridShape g;
+    // the same parameters rounded to FP32 on the host, so FP32 kernels keep
+    // them in scalar registers
+    float inv_tau_f, rho0_f;
+    float thr_f[4][2];
 };
 
 struct D2Q25Args {

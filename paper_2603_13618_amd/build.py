@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-fno-gpu-rdc", "-Wall", "-Wno-unused-function",
+    "-fno-gpu-rdc", "-Wall", "-Wno-unused-function", "-Wl,-z,defs",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 

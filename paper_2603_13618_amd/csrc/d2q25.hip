@@ -230,9 +230,17 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
     const int olds = T::rowbase(ty) + tx;
 
     // ---- stage 25 planes (cells + cross halo) and accumulate the moments.
-    //      All loads are issued before the first LDS write so that the 25
-    //      planes' latencies overlap instead of adding up.
     const R rho0 = R(a.rho0);
+    R drho = R(0), jx = R(0), jy = R(0), edev = R(0);
+    auto moment_add = [&](int i, R v) {
+        const int ia = i / 5, ib = i % 5;
+        drho += v;
+        if (ia != 2) jx += R(gh5_xi(ia)) * v;
+        if (ib != 2) jy += R(gh5_xi(ib)) * v;
+        edev += R(0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))) * v;
+    };
+    // all loads are issued before the first LDS write so that the 25
+    // planes' latencies overlap instead of adding up
     R vin[25], vh[HR][25], vc[25];
     sfor25<25>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
@@ -242,17 +250,12 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
         for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
         vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
     });
-    R drho = R(0), jx = R(0), jy = R(0), edev = R(0);
     sfor25<25>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        constexpr int ia = i / 5, ib = i % 5;
         R* dst = lds + i * T::kPlane;
         const R v = vin[i];
         dst[olds] = v;
-        drho += v;
-        if constexpr (ia != 2) jx += R(gh5_xi(ia)) * v;
-        if constexpr (ib != 2) jy += R(gh5_xi(ib)) * v;
-        edev += R(0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))) * v;
+        moment_add(i, v);
 #pragma unroll
         for (int k = 0; k < HR; ++k)
             if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];

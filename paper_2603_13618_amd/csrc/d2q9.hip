@@ -308,11 +308,26 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
 }
 
 // Fused step with the next row staged through LDS by direct global->LDS
-// loads (16 bytes per lane per population): the row in flight costs no
-// registers, so more waves fit per SIMD.  Each wave owns a private 9 x 1 KB
-// staging area; lane l's 16 bytes of population i land at i*1024 + 16*l and
-// are read back by the same lane.
-template <typename S>
+// loads: the row in flight occupies no registers.  Each wave owns a private
+// 9 x 1 KB staging area.  A lane's VEC cells of population i are CHUNK bytes;
+// they arrive in NP pieces of PS bytes (the direct loads move 1, 2, 4, 12 or
+// 16 bytes per lane), piece p of lane l at i*1024 + p*64*PS + l*PS, and are
+// read back by the same lane.
+// how a lane's VEC cells of one population travel through the staging area
+template <typename S, int VEC> struct StageGeom {
+    static constexpr int CHUNK = VEC * (int)sizeof(typename Store<S>::raw);
+    static constexpr int NP0 = CHUNK == 8 ? 2 : 1;
+    static constexpr int PS0 = CHUNK / NP0;
+    static constexpr int PE0 = PS0 / (int)sizeof(typename Store<S>::raw);
+    // usable when every piece holds whole elements and has a direct-load size
+    static constexpr bool ok = PE0 >= 1 && (PS0 == 1 || PS0 == 2 || PS0 == 4 || PS0 == 16);
+    // (a geometry that is not ok is never launched; keep it compilable)
+    static constexpr int NP = ok ? NP0 : 1;           // pieces per lane
+    static constexpr int PS = ok ? PS0 : 4;           // bytes per piece
+    static constexpr int PE = ok ? PE0 : 1;           // elements per piece
+};
+
+template <typename S, int VEC>
 __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags,
@@ -320,10 +335,10 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
 {
     using R = typename Store<S>::real;
     using raw = typename Store<S>::raw;
-    constexpr int VEC = 16 / (int)sizeof(raw);
+    using G = StageGeom<S, VEC>;
     typedef __attribute__((address_space(1))) void gvoid;
     typedef __attribute__((address_space(3))) void lvoid;
-    __shared__ __attribute__((aligned(16))) unsigned char stage[kBlock / kWave][9][kWave * 16];
+    __shared__ __attribute__((aligned(16))) unsigned char stage[kBlock / kWave][9][1024];
 
     const int nx = a.nx, ny = a.ny;
     const long long plane = a.plane;
@@ -350,7 +365,7 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
     unsigned nfault = 0;
 
-    // x-shifted populations also need one value outside the lane's 16 bytes;
+    // x-shifted populations also need one value outside the lane's cells;
     // only the wave's edge lanes (and the row ends) load it, into registers
     R edge[9];
     auto issue = [&](int y) {
@@ -360,8 +375,17 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             int ys = y - cy;
             ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
             const raw* row = fin + i * plane + (long long)ys * nx;
-            if (active)
-                __builtin_amdgcn_global_load_lds((gvoid*)(row + x0), (lvoid*)&stage[wave][i][0], 16, 0, 0);
+            if (active) {
+#pragma unroll
+                for (int p = 0; p < G::NP; ++p) {
+                    gvoid* g = (gvoid*)(row + x0 + p * G::PE);
+                    lvoid* l = (lvoid*)&stage[wave][i][p * kWave * G::PS];
+                    if constexpr (G::PS == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+                    else if constexpr (G::PS == 4) __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+                    else if constexpr (G::PS == 2) __builtin_amdgcn_global_load_lds(g, l, 2, 0, 0);
+                    else __builtin_amdgcn_global_load_lds(g, l, 1, 0, 0);
+                }
+            }
             if constexpr (cx == 1) {
                 edge[i] = R(0);
                 if (active && (lane == 0 || x0 == 0))
@@ -381,7 +405,14 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             constexpr int i = decltype(ic)::value;
             constexpr int cx = cx9(i);
             R v[VEC];
-            load_vec<S, VEC>(reinterpret_cast<const raw*>(&stage[wave][i][lane * 16]), v);
+#pragma unroll
+            for (int p = 0; p < G::NP; ++p) {
+                R piece[G::PE];
+                load_vec<S, G::PE>(reinterpret_cast<const raw*>(
+                                       &stage[wave][i][p * kWave * G::PS + lane * G::PS]), piece);
+#pragma unroll
+                for (int k = 0; k < G::PE; ++k) v[p * G::PE + k] = piece[k];
+            }
             if constexpr (cx == 0) {
 #pragma unroll
                 for (int k = 0; k < VEC; ++k) cur[i][k] = v[k];
@@ -473,8 +504,8 @@ static hipError_t launch_pass(int pass, const D2Q9Args& a, const void* fin, void
     const dim3 grid(a.g.nblocks), block(kBlock);
     switch (pass) {
     case kFused:
-        if (LKS_D2Q9_LDS_STAGE && VEC * (int)sizeof(raw) == 16)
-            d2q9_fused_lds<S><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        if (LKS_D2Q9_LDS_STAGE && StageGeom<S, VEC>::ok)
+            d2q9_fused_lds<S, VEC><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
         else
             d2q9_kernel<S, VEC, kFused><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
         break;

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 // Occupancy hint for the cell kernels: minimum waves per SIMD the register
 // allocation must allow (0 = let the compiler decide).
@@ -61,18 +62,9 @@ struct bf16_t { uint16_t bits; };
 struct f16_t { uint16_t bits; };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// round to nearest even; NaN stays a (quiet) NaN
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
+// v_cvt_pk_bf16_f32 and v_cvt_pk_f16_f32 round to nearest even (default mode)
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-// v_cvt_f16_f32 rounds to nearest even in the default mode
 __device__ __forceinline__ uint16_t f32_to_f16_rne(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
 
 template <typename S> struct Store;
@@ -158,8 +150,23 @@ __device__ __forceinline__ void store_vec(typename Store<S>::raw* __restrict__ p
 {
     using raw = typename Store<S>::raw;
     Pack<raw, VEC> pk;
+    constexpr bool half = std::is_same<S, bf16_t>::value || std::is_same<S, f16_t>::value;
+    if constexpr (half && VEC % 2 == 0) {
+        // two values per packed conversion
+        using F2 = __attribute__((ext_vector_type(2))) float;
+        using H2 = __attribute__((ext_vector_type(2)))
+            typename std::conditional<std::is_same<S, bf16_t>::value, __bf16, _Float16>::type;
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) pk.v[k] = Store<S>::from_real(in[k]);
+        for (int k = 0; k < VEC; k += 2) {
+            const H2 h = __builtin_convertvector(F2{in[k], in[k + 1]}, H2);
+            const uint32_t u = __builtin_bit_cast(uint32_t, h);
+            pk.v[k] = (uint16_t)(u & 0xffffu);
+            pk.v[k + 1] = (uint16_t)(u >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) pk.v[k] = Store<S>::from_real(in[k]);
+    }
     store_raw_pack(p, pk);
 }
 

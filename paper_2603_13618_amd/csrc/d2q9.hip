@@ -338,7 +338,13 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     using G = StageGeom<S, VEC>;
     typedef __attribute__((address_space(1))) void gvoid;
     typedef __attribute__((address_space(3))) void lvoid;
+    // per wave: one row of the nine planes, and for each x-shifted plane the
+    // one value just outside the wave's span of cells
     __shared__ __attribute__((aligned(16))) unsigned char stage[kBlock / kWave][9][1024];
+    __shared__ __attribute__((aligned(16))) unsigned char halo[kBlock / kWave][9][8];
+    constexpr int ES = (int)sizeof(raw);        // bytes per element
+    constexpr int EP = ES < 4 ? ES : 4;         // bytes per direct-load piece of an edge value
+    constexpr int NEP = ES / EP;                // pieces per edge value
 
     const int nx = a.nx, ny = a.ny;
     const long long plane = a.plane;
@@ -350,6 +356,12 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     const bool active = x0 < nx;
     const int y0 = rg * a.g.rows;
     const int y1 = min(y0 + a.g.rows, ny);
+    // the wave's span of cells and its periodic neighbours (nx % VEC == 0)
+    const int xw = (tx * kBlock + wave * kWave) * VEC;
+    const bool wave_active = xw < nx;
+    const int xl = xw == 0 ? nx - 1 : xw - 1;
+    const int xr = xw + kWave * VEC >= nx ? 0 : xw + kWave * VEC;
+    const bool last_lane = lane == kWave - 1 || x0 + VEC >= nx;
 
     constexpr bool F32 = sizeof(R) == 4;
     const R rho0 = F32 ? R(a.rho0_f) : R(a.rho0);
@@ -365,9 +377,9 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
     unsigned nfault = 0;
 
-    // x-shifted populations also need one value outside the lane's cells;
-    // only the wave's edge lanes (and the row ends) load it, into registers
-    R edge[9];
+    // Row y of every plane into this wave's staging area.  Only direct
+    // global->LDS loads: no register results, so nothing here makes the
+    // wave wait for the loads it has just issued.
     auto issue = [&](int y) {
         static_for<9>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
@@ -386,20 +398,40 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
                     else __builtin_amdgcn_global_load_lds(g, l, 1, 0, 0);
                 }
             }
-            if constexpr (cx == 1) {
-                edge[i] = R(0);
-                if (active && (lane == 0 || x0 == 0))
-                    edge[i] = Store<S>::to_real(row[x0 == 0 ? nx - 1 : x0 - 1]);
-            } else if constexpr (cx == -1) {
-                edge[i] = R(0);
-                if (active && (lane == kWave - 1 || x0 + VEC >= nx))
-                    edge[i] = Store<S>::to_real(row[x0 + VEC >= nx ? 0 : x0 + VEC]);
+            if constexpr (cx != 0) {
+                // lanes 0 .. NEP-1 fetch the pieces of the edge value
+                if (wave_active && lane < NEP) {
+                    const int xe = cx == 1 ? xl : xr;
+                    gvoid* g = (gvoid*)(reinterpret_cast<const unsigned char*>(row + xe) + lane * EP);
+                    lvoid* l = (lvoid*)&halo[wave][i][0];
+                    if constexpr (EP == 4) __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+                    else if constexpr (EP == 2) __builtin_amdgcn_global_load_lds(g, l, 2, 0, 0);
+                    else __builtin_amdgcn_global_load_lds(g, l, 1, 0, 0);
+                }
             }
         });
     };
 
+    // results of one row, stored while the next row computes
+    R res[9][VEC];
+    R s_kl[VEC], s_neq[VEC], s_pi[VEC];
+    uint8_t fl[VEC];
+    auto store_row = [&](int y) {
+        if (active) {
+            const long long off = (long long)y * nx + x0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, res[i]);
+            store_pack<R, VEC>(sens + off, s_kl);
+            store_pack<R, VEC>(sens + plane + off, s_neq);
+            store_pack<R, VEC>(sens + 2 * plane + off, s_pi);
+            store_pack<uint8_t, VEC>(flags + off, fl);
+        }
+    };
+
     if (y0 < y1) issue(y0);
     for (int y = y0; y < y1; ++y) {                 // uniform across the workgroup
+        // row y has landed in LDS (and the stores of row y - 2 have completed)
+        wait_vmem_all();
         R cur[9][VEC];
         static_for<9>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
@@ -416,28 +448,30 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             if constexpr (cx == 0) {
 #pragma unroll
                 for (int k = 0; k < VEC; ++k) cur[i][k] = v[k];
-            } else if constexpr (cx == 1) {
-                R prev = __shfl_up(v[VEC - 1], 1, kWave);
-                if (lane == 0 || x0 == 0) prev = edge[i];
-                cur[i][0] = prev;
-#pragma unroll
-                for (int k = 1; k < VEC; ++k) cur[i][k] = v[k - 1];
             } else {
-                R next = __shfl_down(v[0], 1, kWave);
-                if (lane == kWave - 1 || x0 + VEC >= nx) next = edge[i];
+                const R e = Store<S>::to_real(*reinterpret_cast<const raw*>(&halo[wave][i][0]));
+                if constexpr (cx == 1) {
+                    const R prev = __shfl_up(v[VEC - 1], 1, kWave);
+                    cur[i][0] = lane == 0 ? e : prev;
 #pragma unroll
-                for (int k = 0; k + 1 < VEC; ++k) cur[i][k] = v[k + 1];
-                cur[i][VEC - 1] = next;
+                    for (int k = 1; k < VEC; ++k) cur[i][k] = v[k - 1];
+                } else {
+                    const R next = __shfl_down(v[0], 1, kWave);
+#pragma unroll
+                    for (int k = 0; k + 1 < VEC; ++k) cur[i][k] = v[k + 1];
+                    cur[i][VEC - 1] = last_lane ? e : next;
+                }
             }
         });
         // the staging area is rewritten by the next row's loads only after
         // every lane's reads of this row have completed
-        __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0)
+        wait_lds_all();
         if (y + 1 < y1) issue(y + 1);
-        const long long off = (long long)y * nx + x0;
+        // the previous row's stores go out after the next row's loads, so
+        // the wait for those loads at the top of the next iteration has this
+        // row's whole computation to cover both (stores count in vmcnt too)
+        if (y > y0) store_row(y - 1);
 
-        R s_kl[VEC], s_neq[VEC], s_pi[VEC];
-        uint8_t fl[VEC];
         R rsum[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
@@ -448,7 +482,7 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             LKS_CELL_BARRIER();
             const CellSense<R> cs = cell_update<R, true, true>(dc, rho0, inv_tau, drho, jx, jy);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) cur[i][k] = dc[i];
+            for (int i = 0; i < 9; ++i) res[i][k] = dc[i];
             int level = 0;
             const R sv[3] = {cs.kl, cs.neq, cs.pi};
 #pragma unroll
@@ -478,15 +512,8 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
         acc[4] += (double)rsum[3];
         acc[5] += (double)rsum[4];
         acc[6] += (double)rsum[5];
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, cur[i]);
-            store_pack<R, VEC>(sens + off, s_kl);
-            store_pack<R, VEC>(sens + plane + off, s_neq);
-            store_pack<R, VEC>(sens + 2 * plane + off, s_pi);
-            store_pack<uint8_t, VEC>(flags + off, fl);
-        }
     }
+    if (y0 < y1) store_row(y1 - 1);
     if (nfault) atomicAdd(faults, (unsigned long long)nfault);
     block_sums(acc, partials + (long long)blockIdx.x * kNsums);
 }

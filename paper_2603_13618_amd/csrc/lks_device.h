@@ -234,6 +234,26 @@ template <typename R>
 __device__ __forceinline__ R kl_dphi(R x) { return log1p_r(x); }
 
 // ---------------------------------------------------------------------------
+// Explicit waits for kernels that stage through LDS with direct global->LDS
+// loads.  The compiler does not reliably order LDS reads after such loads, so
+// the kernels wait themselves; the empty asm statements keep the compiler from
+// moving memory accesses across the wait.  s_waitcnt immediates (gfx9
+// encoding): vmcnt in bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wait_vmem_all()        // vmcnt(0)
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void wait_lds_all()         // lgkmcnt(0)
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    asm volatile("" ::: "memory");
+}
+
+// ---------------------------------------------------------------------------
 // Reductions: wave64 butterfly in FP64, then across the 4 waves via LDS.
 // Deterministic for a fixed launch shape.
 // ---------------------------------------------------------------------------

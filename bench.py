@@ -30,6 +30,9 @@ BYTES_F32_FUSED = 85            # 9 x 4 read + 9 x 4 written + 3 x 4 sensors + 1
 BYTES_F32_PLAIN = 193           # stream 36 + 36, sensors 36 + 13, collide 36 + 36
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2q9_fused_f32_4096.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_13618_amd", "csrc", "d2q9.hip")
+# the fused FP32 step at the default launch shape (4 cells per thread)
+FUSED_KERNEL = "d2q9_fused_lds<float,4>"
+FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 
 
 def parse():
@@ -95,8 +98,8 @@ def assemble_traffic(dirs):
     from paper_2603_13618_amd import workloads
     n = workloads.SMOOTH_4096["nx"]
     copy_bytes = 9 * n * n * 4
-    fetch, nf = _pmc_mean(dirs[0], "FETCH_SIZE", "d2q9_kernel")
-    write, nw = _pmc_mean(dirs[1], "WRITE_SIZE", "d2q9_kernel")
+    fetch, nf = _pmc_mean(dirs[0], "FETCH_SIZE", FUSED_KERNEL_PREFIX)
+    write, nw = _pmc_mean(dirs[1], "WRITE_SIZE", FUSED_KERNEL_PREFIX)
     cfetch, _ = _pmc_mean(dirs[2], "FETCH_SIZE", "copy_kernel")
     cwrite, _ = _pmc_mean(dirs[3], "WRITE_SIZE", "copy_kernel")
     kf = copy_bytes / (cfetch * 1024.0)
@@ -104,7 +107,7 @@ def assemble_traffic(dirs):
     read_b = fetch * 1024.0 * kf
     write_b = write * 1024.0 * kw
     out = {
-        "kernel": "d2q9_kernel<float,4,fused>", "cells": n * n, "kernel_hash": kernel_hash(),
+        "kernel": FUSED_KERNEL, "cells": n * n, "kernel_hash": kernel_hash(),
         "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
         "copy_fetch_kib": cfetch, "copy_write_kib": cwrite, "copy_bytes_each_way": copy_bytes,
         "fetch_scale": kf, "write_scale": kw,
@@ -211,6 +214,7 @@ def main():
     t_kernel = s.elapsed_time(e) / reps * 1e-3
     achieved = BYTES_F32_FUSED * n * n / t_kernel / 1e9
     traffic = traffic_entry(n * n)
+    copy_gbps = copy_ceiling(torch, lks, dev, ev, 9 * n * n * 4)
 
     # ---- the unfused baseline (three passes per step) on the same state
     lat.init(rho, ux, uy)
@@ -250,9 +254,11 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "kernel": "d2q9_kernel<float,4,fused>",
+            "kernel": FUSED_KERNEL,
             "bytes_per_launch": BYTES_F32_FUSED * n * n,
             "kernel_us": round(t_kernel * 1e6, 2),
+            "copy_GBps": round(copy_gbps, 1),
+            "frac_of_copy": round(achieved / copy_gbps, 4),
         },
         "plain": {
             "MLUPS": round(n * n / t_plain / 1e6, 1),
@@ -273,6 +279,26 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def copy_ceiling(torch, lks, dev, ev, nbytes):
+    """Rate of the library's plain copy kernel over one population buffer's
+    worth of bytes (read + write), GB/s."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    lks.copy_probe(b, a)
+    torch.cuda.synchronize()
+    s, e = ev(), ev()
+    reps = 20
+    s.record()
+    for _ in range(reps):
+        lks.copy_probe(b, a)
+    e.record()
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / reps * 1e-3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / t / 1e9
 
 
 def kernel_only(args, torch, lks, inputs, workloads, dev):
@@ -335,10 +361,19 @@ def time_forms(torch, lks, inputs, workloads, dev, ev):
     return res
 
 
+def host_threads():
+    """Cores this process may use (affinity mask, capped by OMP_NUM_THREADS)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(n, 1)
+
+
 def cpu_baseline(steps, rho, ux, uy, wl):
     """The FP64 oracle on the host cores: the full 4096^2 grid for a few steps."""
     import oracle
-    threads = os.cpu_count() or 1
+    threads = host_threads()
     f0 = oracle.equilibrium(9, rho, ux, uy)
     oracle.run(9, f0, 1, tau=wl["tau"], nthreads=threads)          # page-in
     t0 = time.perf_counter()

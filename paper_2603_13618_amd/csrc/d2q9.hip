@@ -319,8 +319,11 @@ template <typename S, int VEC> struct StageGeom {
     static constexpr int NP0 = CHUNK == 8 ? 2 : 1;
     static constexpr int PS0 = CHUNK / NP0;
     static constexpr int PE0 = PS0 / (int)sizeof(typename Store<S>::raw);
-    // usable when every piece holds whole elements and has a direct-load size
-    static constexpr bool ok = PE0 >= 1 && (PS0 == 1 || PS0 == 2 || PS0 == 4 || PS0 == 16);
+    // usable when every piece holds whole elements and is a whole number of
+    // dwords: a sub-dword direct load writes lane l's value into the 4-byte
+    // LDS slot l, not at (piece size) x l, so 1- and 2-byte pieces would not
+    // land contiguously
+    static constexpr bool ok = PE0 >= 1 && (PS0 == 4 || PS0 == 16);
     // (a geometry that is not ok is never launched; keep it compilable)
     static constexpr int NP = ok ? NP0 : 1;           // pieces per lane
     static constexpr int PS = ok ? PS0 : 4;           // bytes per piece
@@ -393,13 +396,12 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
                     gvoid* g = (gvoid*)(row + x0 + p * G::PE);
                     lvoid* l = (lvoid*)&stage[wave][i][p * kWave * G::PS];
                     if constexpr (G::PS == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
-                    else if constexpr (G::PS == 4) __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
-                    else if constexpr (G::PS == 2) __builtin_amdgcn_global_load_lds(g, l, 2, 0, 0);
-                    else __builtin_amdgcn_global_load_lds(g, l, 1, 0, 0);
+                    else __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
                 }
             }
             if constexpr (cx != 0) {
-                // lanes 0 .. NEP-1 fetch the pieces of the edge value
+                // lanes 0 .. NEP-1 fetch the pieces of the edge value (for a
+                // 16-bit value only lane 0, whose LDS slot starts at offset 0)
                 if (wave_active && lane < NEP) {
                     const int xe = cx == 1 ? xl : xr;
                     gvoid* g = (gvoid*)(reinterpret_cast<const unsigned char*>(row + xe) + lane * EP);

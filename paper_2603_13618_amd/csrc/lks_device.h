@@ -29,7 +29,7 @@
 #define LKS_D2Q9_PREFETCH 1
 #endif
 // 1 = the fused D2Q9 step stages the next row through LDS with direct
-// global->LDS loads where a lane's cells span 16 bytes (FP32 x 4, FP64 x 2).
+// global->LDS loads where a lane's cells span whole dwords (4, 8 or 16 bytes).
 #ifndef LKS_D2Q9_LDS_STAGE
 #define LKS_D2Q9_LDS_STAGE 1
 #endif
@@ -61,11 +61,22 @@ constexpr int kNsums = 8;
 struct bf16_t { uint16_t bits; };
 struct f16_t { uint16_t bits; };
 
+// The 16-bit forms store the FP32 result rounded to nearest even.  The
+// conversion must start from that FP32 value: left alone, the compiler folds
+// a float->half conversion into the FMA that produced the value
+// (v_fma_mix*), rounding once from the exact product-sum, which differs from
+// rounding the FP32 result on exact FP16 ties.  pin_f32 makes the value
+// opaque (an empty asm on its register), so the conversion is a separate
+// instruction (v_cvt_*, round to nearest even in the default mode).
+__device__ __forceinline__ float pin_f32(float f)
+{
+    asm("" : "+v"(f));
+    return f;
+}
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// v_cvt_pk_bf16_f32 and v_cvt_pk_f16_f32 round to nearest even (default mode)
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)pin_f32(f)); }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) { return __builtin_bit_cast(uint16_t, (_Float16)pin_f32(f)); }
 
 template <typename S> struct Store;
 template <> struct Store<double> {
@@ -158,7 +169,7 @@ __device__ __forceinline__ void store_vec(typename Store<S>::raw* __restrict__ p
             typename std::conditional<std::is_same<S, bf16_t>::value, __bf16, _Float16>::type;
 #pragma unroll
         for (int k = 0; k < VEC; k += 2) {
-            const H2 h = __builtin_convertvector(F2{in[k], in[k + 1]}, H2);
+            const H2 h = __builtin_convertvector(F2{pin_f32(in[k]), pin_f32(in[k + 1])}, H2);
             const uint32_t u = __builtin_bit_cast(uint32_t, h);
             pk.v[k] = (uint16_t)(u & 0xffffu);
             pk.v[k + 1] = (uint16_t)(u >> 16);

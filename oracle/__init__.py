@@ -14,5 +14,7 @@ from .oracle import (  # noqa: F401
     d2q25_step,
     run,
     flags_from_sensors,
+    ext_sensors,
+    EXT_NAMES,
     NSUMS,
 )

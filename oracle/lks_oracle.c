@@ -32,6 +32,10 @@
  *       S_NEQ = sum_i |f_i - f^eq_i|                  (Sec. III.B.2, eq. sensor-neq-kin, f term)
  *       S_PI  = || sum_i v_i v_i f^neq_i ||_F          (Sec. III.A.1, eq. sensor-TauNS-kin)
  *       S_Q   = || sum_i v_i (|v_i|^2/2) f^neq_i ||_2  (Sec. III.A.6, eq. sensor-qNSF-kin-ryk, g = 0)
+ *   - extended sensors on demand (orc_ext_sensors): the rest of Table I on
+ *     the f distribution -- Knudsen, relative H, H dissipation, KL
+ *     dissipation, entropic estimate, rate of shear, viscous heating, Fourier
+ *     flux (D2Q25), rate of compression and rate of strain (D2Q9);
  *   - refinement flags (Sec. II.B.2, regridding step 1): per enabled sensor
  *     level = [s > theta1] + [s > theta2]; flag = max over sensors; a cell
  *     whose f_i or f^eq_i is not strictly positive (Sec. III.C, positivity
@@ -335,6 +339,155 @@ long orc_sensors(int lattice, long n, const double* f, double* out)
         for (int k = 0; k < 4; ++k) out[(long)k * n + c] = s[k];
     }
     return faults;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Extended sensors (the rest of Table I on the f distribution)             */
+/* ------------------------------------------------------------------------ */
+
+/* Order of the extended sensor planes. */
+enum {
+    ORC_X_KN = 0,      /* sum |f^neq/f^eq|                  (Sec. III.B.1, eq. sensor-Knudsen-kin_f)   */
+    ORC_X_HR,          /* |H(f) - H(f^eq)|, H = sum f ln(f/w)  (Sec. III.B.4, eq. Hneq-sensor, f term)  */
+    ORC_X_SIGMA_H,     /* -sum Omega ln(f/w)                 (Sec. III.B.5, eq. Dissip-H-sensor)        */
+    ORC_X_SIGMA_HKL,   /* -sum Omega ln(f/f^eq)              (Sec. III.B.5, eq. Dissip-HKL-sensor)      */
+    ORC_X_ALPHA,       /* |2 - alpha_f|, polynomial estimate (Sec. III.B.6, eqs. sensor-alpha-kin,
+                          alpha-polynomial-1/2)                                                         */
+    ORC_X_SHEAR,       /* |(1/mu)[(1/D) tr(P) I - P]|_F      (Sec. III.A.3, eq. sensor-S-kin)           */
+    ORC_X_QH,          /* |u . P|                            (Sec. III.A.5, eq. sensor-qH-kin)          */
+    ORC_X_QF,          /* |q^neq - u . P| (D2Q25)            (Sec. III.A.7, eq. sensor-qF-kin-ryk, g=0) */
+    ORC_X_COMP,        /* sqrt(D)|tr P|/|2 mu + D lambda| (D2Q9) (Sec. III.A.2, eq. sensor-C-kin)        */
+    ORC_X_STRAIN,      /* |(1/2mu)[lambda/(D eta) tr(P) I - P]|_F (D2Q9) (Sec. III.A.4, eq. sensor-E-kin) */
+    ORC_NEXT
+};
+
+/* Extended sensors of one cell from its populations f and equilibrium feq.
+ * P = sum v v f^neq, q^neq = sum v |v|^2/2 f^neq, u = sum v f / sum f.
+ * The collision is single-relaxation BGK, Omega_i = -(f_i - f^eq_i)/tau, with
+ * tau the lattice relaxation time on D2Q9 and mu/(rho T) on D2Q25.
+ * Viscosities: on D2Q25 mu is the model's dynamic viscosity; the monatomic
+ * gas (C_v = D R/2) has lambda = -mu and eta = 0, so the rate-of-compression
+ * and rate-of-strain sensors have a zero denominator there and are not
+ * defined (left 0).  On the isothermal D2Q9 lattice the pre-collision
+ * non-equilibrium stress is -tau rho c_s^2 (grad u + grad u^T) with no
+ * separate trace term, i.e. mu = tau rho c_s^2 and lambda = 0 (eta = mu).
+ * Cells with f_i <= 0 or f^eq_i <= 0 get +inf for the five sensors that
+ * take logarithms or ratios of populations.
+ * The entropic estimate follows the printed polynomial with f^neq = f - f^eq
+ * as the paper defines it.  That polynomial is not the series solution of
+ * its defining condition (eq. H-mirr-equal): the exact root is
+ * alpha = 2 - (1/3) sum f^neq^3/f^2 / sum f^neq^2/f + O(y^2), the polynomial's
+ * first correction is -4 times that, and the higher terms differ in structure.
+ * Pinned at leading order only; |2 - alpha_f| = 0 when a_1 = 0. */
+static void cell_ext_sensors(const orc_rule* r, const double* f, const double* feq, int lattice,
+                             double par, double* s)
+{
+    const int D = 2;
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    double kn = 0.0, hf = 0.0, heq = 0.0, sig_h = 0.0, sig_hkl = 0.0;
+    double an[5] = {0, 0, 0, 0, 0};
+    double pxx = 0.0, pxy = 0.0, pyy = 0.0, qx = 0.0, qy = 0.0;
+    int fault = 0;
+    for (int a = 0; a < r->q1; ++a)
+        for (int b = 0; b < r->q1; ++b) {
+            const int i = r->q1 * a + b;
+            const double vx = r->v[a], vy = r->v[b];
+            rho += f[i];
+            jx += vx * f[i];
+            jy += vy * f[i];
+            const double fn = f[i] - feq[i];
+            pxx += vx * vx * fn;
+            pxy += vx * vy * fn;
+            pyy += vy * vy * fn;
+            const double e = 0.5 * (vx * vx + vy * vy);
+            qx += vx * e * fn;
+            qy += vy * e * fn;
+        }
+    const double ux = jx / rho, uy = jy / rho;
+    /* relaxation time and viscosity */
+    double tau, mu;
+    if (lattice == 9) {
+        tau = par;
+        mu = tau * rho * r->tref;
+    } else {
+        const orc_mom m = moments(r, f);
+        mu = par;
+        tau = mu / (m.rho * m.T);
+    }
+    for (int a = 0; a < r->q1; ++a)
+        for (int b = 0; b < r->q1; ++b) {
+            const int i = r->q1 * a + b;
+            const double w = r->w[a] * r->w[b];
+            if (!(f[i] > 0.0) || !(feq[i] > 0.0)) {
+                fault = 1;
+                continue;
+            }
+            const double fn = f[i] - feq[i];
+            const double omega = -fn / tau;
+            kn += fabs(fn / feq[i]);
+            hf += f[i] * log(f[i] / w);
+            heq += feq[i] * log(feq[i] / w);
+            sig_h -= omega * log(f[i] / w);
+            sig_hkl -= omega * log(f[i] / feq[i]);
+            for (int n = 1; n <= 4; ++n) an[n] += pow(fn, n + 1) / pow(f[i], n);
+        }
+    for (int n = 1; n <= 4; ++n) an[n] *= ((n % 2) ? 1.0 : -1.0) / (n * (n + 1.0));
+    double alpha_dev = 0.0;           /* 2 - alpha_f */
+    if (an[1] != 0.0) {
+        const double r2 = an[2] / an[1], r3 = an[3] / an[1], r4 = an[4] / an[1];
+        const double alpha = 2.0 - 4.0 * r2 + 16.0 * r2 * r2 - 8.0 * r3 + 80.0 * r2 * r3
+                             - 80.0 * r2 * r2 * r2 - 16.0 * r4;
+        alpha_dev = 2.0 - alpha;
+    }
+    const double tr = pxx + pyy;
+    /* rate of shear: (1/mu) [(tr/D) I - P] */
+    const double sxx = (tr / D - pxx) / mu, syy = (tr / D - pyy) / mu, sxy = -pxy / mu;
+    /* viscous heating u . P and the Fourier part q^neq - u . P */
+    const double hx = ux * pxx + uy * pxy, hy = ux * pxy + uy * pyy;
+    s[ORC_X_KN] = fault ? INFINITY : kn;
+    s[ORC_X_HR] = fault ? INFINITY : fabs(hf - heq);
+    s[ORC_X_SIGMA_H] = fault ? INFINITY : sig_h;
+    s[ORC_X_SIGMA_HKL] = fault ? INFINITY : sig_hkl;
+    s[ORC_X_ALPHA] = fault ? INFINITY : fabs(alpha_dev);
+    s[ORC_X_SHEAR] = sqrt(sxx * sxx + 2.0 * sxy * sxy + syy * syy);
+    s[ORC_X_QH] = sqrt(hx * hx + hy * hy);
+    if (lattice == 25) {
+        s[ORC_X_QF] = sqrt((qx - hx) * (qx - hx) + (qy - hy) * (qy - hy));
+        s[ORC_X_COMP] = 0.0;
+        s[ORC_X_STRAIN] = 0.0;
+    } else {
+        const double lambda = 0.0, eta = 2.0 * mu / D + lambda;
+        s[ORC_X_QF] = 0.0;
+        s[ORC_X_COMP] = sqrt((double)D) * fabs(tr) / fabs(2.0 * mu + D * lambda);
+        const double c = lambda / (D * eta);
+        const double exx = (c * tr - pxx) / (2.0 * mu), eyy = (c * tr - pyy) / (2.0 * mu),
+                     exy = -pxy / (2.0 * mu);
+        s[ORC_X_STRAIN] = sqrt(exx * exx + 2.0 * exy * exy + eyy * eyy);
+    }
+}
+
+int orc_num_ext(void) { return ORC_NEXT; }
+
+/* Extended sensors of n cells given their (pre-collision) populations
+ * f[Q][n]: out[ORC_NEXT][n].  par = tau on D2Q9, mu on D2Q25.  The
+ * equilibrium is built from each cell's own moments. */
+int orc_ext_sensors(int lattice, long n, const double* f, double par, double* out)
+{
+    orc_rule r;
+    if (lattice == 9) rule_d2q9(&r);
+    else if (lattice == 25) rule_d2q25(&r);
+    else return -1;
+    const int Q = r.q1 * r.q1;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) {
+        double fc[ORC_MAXQ], fe[ORC_MAXQ], s[ORC_NEXT];
+        for (int i = 0; i < Q; ++i) fc[i] = f[(long)i * n + c];
+        orc_mom m = moments(&r, fc);
+        grad_hermite_feq(&r, m.rho, m.ux, m.uy, lattice == 9 ? r.tref : m.T, fe);
+        cell_ext_sensors(&r, fc, fe, lattice, par, s);
+        for (int k = 0; k < ORC_NEXT; ++k) out[(long)k * n + c] = s[k];
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

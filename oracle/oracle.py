@@ -56,6 +56,8 @@ def _load():
         lib.orc_run.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, P, P, P, P, P, P,
                                 ctypes.c_int]
         lib.orc_run.restype = ctypes.c_long
+        lib.orc_ext_sensors.argtypes = [ctypes.c_int, ctypes.c_long, P, ctypes.c_double, P]
+        lib.orc_num_ext.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -102,6 +104,23 @@ def sensors(q, f):
     out = np.empty((4,) + f.shape[1:])
     nf = _load().orc_sensors(q, f[0].size, _p(f), _p(out))
     return out, int(nf)
+
+
+# extended sensor planes, in the order orc_ext_sensors writes them
+EXT_NAMES = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf", "comp", "strain")
+
+
+def ext_sensors(q, f, par):
+    """The extended sensors [len(EXT_NAMES), *shape] of populations f (the
+    pre-collision state), equilibrium from their own moments; par = tau on
+    D2Q9, mu on D2Q25."""
+    f = _f64(f)
+    lib = _load()
+    assert lib.orc_num_ext() == len(EXT_NAMES)
+    out = np.empty((len(EXT_NAMES),) + f.shape[1:])
+    if lib.orc_ext_sensors(q, f[0].size, _p(f), float(par), _p(out)) != 0:
+        raise ValueError(q)
+    return out
 
 
 def _thr(thr):

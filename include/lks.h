@@ -16,7 +16,9 @@
  *   - in the same pass, on the pre-collision populations of the step, the
  *     sensors S_KL (eq. HKL-sensor), S_NEQ (eq. sensor-neq-kin), S_PI
  *     (eq. sensor-TauNS-kin) and, on D2Q25, S_Q (eq. sensor-qNSF-kin-ryk,
- *     g = 0), and the per-cell refinement flag (Sec. II.B.2, regridding step 1).
+ *     g = 0), and the per-cell refinement flag (Sec. II.B.2, regridding step 1);
+ *   - optionally, in the same pass, the rest of Table I on the f distribution
+ *     (the LKS_X_* extension sensors below).
  *
  * Conventions
  *   Layout: structure of arrays, plane-major [k][ny][nx], x fastest.
@@ -27,10 +29,14 @@
  *     even); all arithmetic is FP32 (FP64 for F64 storage); global sums are
  *     FP64.
  *   Sensors: plane s = 0 S_KL, 1 S_NEQ, 2 S_PI, 3 S_Q (D2Q25 only), so D2Q9
- *     has 3 planes and D2Q25 4.  float, or double for F64 storage.
+ *     has 3 base planes and D2Q25 4; then one plane per extension sensor in
+ *     ext_mask, in increasing bit order (lks_sensor_planes counts them).
+ *     float, or double for F64 storage.
  *   Flags: uint8 per cell; bits 0-1 = refinement level = max over the sensors
- *     in flag_mask of [s > thr[s][0]] + [s > thr[s][1]]; bit 7 = positivity
- *     fault (some f_i or f^eq_i not > 0, or NaN: S_KL = +inf, level 2).
+ *     enabled in flag_mask (base sensor s: bit s, thresholds thr[s]; extension
+ *     sensor k: bit LKS_FLAG_X(k), thresholds thr_ext[k]) of
+ *     [s > theta1] + [s > theta2]; bit 7 = positivity fault (some f_i or
+ *     f^eq_i not > 0, or NaN: S_KL = +inf, level 2).
  *   Sums: per step LKS_NSUMS doubles: total mass, x- and y-momentum, total
  *     energy (0 on D2Q9), then the totals of S_KL, S_NEQ, S_PI, S_Q over all
  *     cells, all of the pre-collision state.  Step k (counted from 1 since
@@ -77,6 +83,37 @@ enum { LKS_F64 = 0, LKS_F32 = 1, LKS_BF16 = 2, LKS_F16 = 3 };
 enum { LKS_PERIODIC = 0, LKS_OUTFLOW = 1 };
 enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u };
 
+/* Extension sensors (bit k of ext_mask), the rest of Table I evaluated on the
+ * f distribution in the same pass, on the pre-collision populations; BGK
+ * collision Omega_i = -(f_i - f^eq_i)/tau, P = sum v v f^neq, q^neq =
+ * sum v |v|^2/2 f^neq, u = sum v f / sum f; D2Q9 in lattice units with
+ * mu = tau rho c_s^2 (c_s^2 = 1/3) and lambda = 0, D2Q25 with the configured
+ * mu.  F32 or F64 storage and fused steps only.
+ *   KN        sum |f^neq/f^eq|                    Sec. III.B.1, eq. sensor-Knudsen-kin_f
+ *   HR        |H(f) - H(f^eq)|, H = sum f ln(f/w)  Sec. III.B.4, eq. Hneq-sensor (f term)
+ *   SIGMA_H   -sum Omega ln(f/w)                  Sec. III.B.5, eq. Dissip-H-sensor (f term)
+ *   SIGMA_HKL -sum Omega ln(f/f^eq)               Sec. III.B.5, eq. Dissip-HKL-sensor (f term)
+ *   ALPHA     |2 - alpha_f|, the printed polynomial with f^neq = f - f^eq
+ *                                                 Sec. III.B.6, eqs. sensor-alpha-kin,
+ *                                                 alpha-polynomial-1/2
+ *   SHEAR     |(1/mu)[(tr P / D) I - P]|_F        Sec. III.A.3, eq. sensor-S-kin
+ *   QH        |u . P|                             Sec. III.A.5, eq. sensor-qH-kin
+ *   QF        |q^neq - u . P|  (D2Q25 only)       Sec. III.A.7, eq. sensor-qF-kin-ryk (g = 0)
+ *   COMP      sqrt(D) |tr P| / (2 mu)  (D2Q9 only) Sec. III.A.2, eq. sensor-C-kin
+ *   STRAIN    |P|_F / (2 mu)  (D2Q9 only)         Sec. III.A.4, eq. sensor-E-kin
+ * COMP and STRAIN divide by 2 mu + D lambda and eta, which vanish for the
+ * monatomic D2Q25 gas (lambda = -mu); QF needs the energy flux D2Q9 lacks.
+ * Cells with a positivity fault get +inf for KN, HR, SIGMA_H, SIGMA_HKL and
+ * ALPHA. */
+#define LKS_MAX_EXT 10
+enum {
+    LKS_X_KN = 1u << 0, LKS_X_HR = 1u << 1, LKS_X_SIGMA_H = 1u << 2, LKS_X_SIGMA_HKL = 1u << 3,
+    LKS_X_ALPHA = 1u << 4, LKS_X_SHEAR = 1u << 5, LKS_X_QH = 1u << 6, LKS_X_QF = 1u << 7,
+    LKS_X_COMP = 1u << 8, LKS_X_STRAIN = 1u << 9
+};
+/* flag_mask bit of extension sensor k (k = 0 .. LKS_MAX_EXT-1) */
+#define LKS_FLAG_X(k) (1u << (8 + (k)))
+
 typedef struct {
     int32_t lattice;      /* LKS_D2Q9 or LKS_D2Q25                              */
     int32_t nx, ny;       /* grid size, >= 1 each (D2Q9 and periodic D2Q25
@@ -97,11 +134,17 @@ typedef struct {
     int32_t launch_vec;   /* cells per thread along x of the cell kernels (1, 2
                              or 4); 0 picks the widest the row length and the
                              buffer alignment allow (a launch-shape hint only) */
+    uint32_t ext_mask;    /* extension sensors to compute and store, LKS_X_*
+                             bits (0 = none)                                   */
+    int32_t ext_reserved; /* must be 0                                          */
+    double thr_ext[LKS_MAX_EXT][2]; /* (theta1 <= theta2) per extension sensor,
+                             used when its LKS_FLAG_X bit is in flag_mask      */
 } lks_config;
 
 typedef struct {
     void* pop[2];         /* [Q][ny][nx] dtype, ping-pong state buffers        */
-    void* sensors;        /* [nsens][ny][nx] float (double for F64)            */
+    void* sensors;        /* [lks_sensor_planes(cfg)][ny][nx] float (double for
+                             F64): base planes, then the extension planes     */
     uint8_t* flags;       /* [ny][nx]                                          */
     double* sums;         /* [max_steps][LKS_NSUMS]                            */
     void* scratch;        /* >= lks_scratch_bytes(cfg) bytes, 256-B aligned    */
@@ -112,8 +155,12 @@ typedef struct {
  * sums and counters).  0 for an invalid configuration. */
 size_t lks_scratch_bytes(const lks_config* cfg);
 
-/* Number of sensor planes of a lattice (3 for D2Q9, 4 for D2Q25), 0 if invalid. */
+/* Number of base sensor planes of a lattice (3 for D2Q9, 4 for D2Q25), 0 if invalid. */
 int32_t lks_num_sensors(int32_t lattice);
+
+/* Sensor planes a configuration writes: the base planes plus one per
+ * extension bit in ext_mask.  0 for an invalid configuration. */
+int32_t lks_sensor_planes(const lks_config* cfg);
 
 /* Validate cfg and buffers and create a context bound to hip_stream (a
  * hipStream_t; NULL = the null stream).  No kernel is launched. */

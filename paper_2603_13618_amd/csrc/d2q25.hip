@@ -170,7 +170,7 @@ __device__ __forceinline__ void block_sums_n(double (&acc)[kNsums], double* __re
     }
 }
 
-template <typename S, int TX, int TY>
+template <typename S, int TX, int TY, bool EXT = false>
 __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typename Store<S>::raw* __restrict__ fin,
                                                    typename Store<S>::raw* __restrict__ fout,
                                                    typename Store<S>::real* __restrict__ sens,
@@ -277,6 +277,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
     R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0), qy = R(0);
     R xmin = R(0), xmax = R(0), feqmin = R(0);
     bool first = true;
+    ExtAcc<R> xa;
     const long long off = (long long)Y * nx + X;
     d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
         const int i = 5 * ia + ib;
@@ -285,6 +286,11 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
         const R fneq = d - deq;
         const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
         const R x = fneq * rcp(feq);
+        if constexpr (EXT) {
+            // ln(f^eq/w) = ln(rho0 + deq/w); f = w rho0 + d
+            const R lq = log1p_r((rho0 - R(1)) + deq * R(1.0 / (gh5_w(ia) * gh5_w(ib))));
+            xa.add(fneq, x, R(gh5_w(ia) * gh5_w(ib)) * rho0 + d, lq);
+        }
         kl += (fneq * x) * kl_series(x);           // series branch; fallback below
         xmin = first ? x : fmin(xmin, x);
         xmax = first ? fabs(x) : fmax(xmax, fabs(x));
@@ -338,6 +344,21 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
                 level = l > level ? l : level;
             }
         }
+        if constexpr (EXT) {
+            // tau = mu/(rho T), the configured mu
+            R xv[kNumExt];
+            const R inv_mu = R(1.0 / a.mu);
+            ext_finish<R>(xa, kl, fault, rho * (R(1) + tm1) * inv_mu, inv_mu, pxx, pxy, pyy, ux, uy,
+                          qx, qy, true, xv);
+#pragma unroll
+            for (int q = 0; q < kNumExt; ++q) {
+                if (a.x.plane[q] >= 0) sens[a.x.plane[q] * plane + off] = xv[q];
+                if (a.mask & (1u << (kExtFlagShift + q))) {
+                    const int l = (xv[q] > R(a.x.thr[q][0])) + (xv[q] > R(a.x.thr[q][1]));
+                    level = l > level ? l : level;
+                }
+            }
+        }
         sens[off] = s_kl;
         sens[plane + off] = neq;
         sens[2 * plane + off] = s_pi;
@@ -363,8 +384,12 @@ static hipError_t launch_tile(const D2Q25Args& a, const void* fin, void* fout, v
     using raw = typename Store<S>::raw;
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
-    d2q25_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
-        a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    if (a.x.mask)
+        d2q25_kernel<S, TX, TY, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else
+        d2q25_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     return hipGetLastError();
 }
 

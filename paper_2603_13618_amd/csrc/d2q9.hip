@@ -80,10 +80,12 @@ template <typename R> struct CellSense {
 };
 
 // One cell: moments, equilibrium, sensors and (if COLLIDE) the BGK collision
-// of the pre-collision deviations d[0..8] in place.
-template <typename R, bool SENSE, bool COLLIDE>
+// of the pre-collision deviations d[0..8] in place.  EXT: also the extension
+// sensors into ext[0..kNumExt) (mu = tau rho c_s^2, lambda = 0 on this
+// isothermal lattice).
+template <typename R, bool SENSE, bool COLLIDE, bool EXT = false>
 __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau, R& drho_out,
-                                                    R& jx_out, R& jy_out)
+                                                    R& jx_out, R& jy_out, R* ext = nullptr)
 {
     // moments of the deviation form: rho - rho0 = sum d, j = sum c d
     const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
@@ -122,11 +124,17 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
     if constexpr (SENSE) {
         R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
         R xmax = R(0), xmin = R(0), feqmin = R(0);
+        ExtAcc<R> xa;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const R fneq = d[i] - deq[i];
             const R feq = w9<R>(i) * rho0 + deq[i];
             const R x = fneq * rcp(feq);
+            if constexpr (EXT) {
+                // ln(f^eq/w) = ln(rho0 + deq/w); f = w rho0 + d
+                const R lq = log1p_r((rho0 - R(1)) + deq[i] * R(1.0 / w9<double>(i)));
+                xa.add(fneq, x, w9<R>(i) * rho0 + d[i], lq);
+            }
             // S_KL term feq phi(x) = fneq x p(x) on the series branch
             kl += (fneq * x) * kl_series(x);
             xmax = i == 0 ? fabs(x) : fmax(xmax, fabs(x));
@@ -149,6 +157,14 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
         out.kl = out.fault ? R(INFINITY) : kl;
         out.neq = neq;
         out.pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+        if constexpr (EXT) {
+            R xv[kNumExt];
+            const R inv_mu = R(3) * inv_tau * irho;          // mu = tau rho / 3
+            ext_finish<R>(xa, kl, out.fault, inv_tau, inv_mu, pxx, pxy, pyy, ux, uy, R(0), R(0),
+                          false, xv);
+#pragma unroll
+            for (int k = 0; k < kNumExt; ++k) ext[k] = xv[k];
+        }
     }
     if constexpr (COLLIDE) {
 #pragma unroll
@@ -330,7 +346,7 @@ template <typename S, int VEC> struct StageGeom {
     static constexpr int PE = ok ? PE0 : 1;           // elements per piece
 };
 
-template <typename S, int VEC>
+template <typename S, int VEC, bool EXT = false>
 __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags,
@@ -475,14 +491,16 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
         if (y > y0) store_row(y - 1);
 
         R rsum[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+        R xres[EXT ? kNumExt : 1][VEC];
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
             R dc[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) dc[i] = cur[i][k];
             R drho, jx, jy;
+            R xv[kNumExt];
             LKS_CELL_BARRIER();
-            const CellSense<R> cs = cell_update<R, true, true>(dc, rho0, inv_tau, drho, jx, jy);
+            const CellSense<R> cs = cell_update<R, true, true, EXT>(dc, rho0, inv_tau, drho, jx, jy, xv);
 #pragma unroll
             for (int i = 0; i < 9; ++i) res[i][k] = dc[i];
             int level = 0;
@@ -492,6 +510,18 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
                 if (a.mask & (1u << s)) {
                     const int l = (sv[s] > th[s][0]) + (sv[s] > th[s][1]);
                     level = l > level ? l : level;
+                }
+            }
+            if constexpr (EXT) {
+#pragma unroll
+                for (int q = 0; q < kNumExt; ++q) {
+                    xres[q][k] = xv[q];
+                    if (a.mask & (1u << (kExtFlagShift + q))) {
+                        const R t0 = F32 ? R(a.x.thr_f[q][0]) : R(a.x.thr[q][0]);
+                        const R t1 = F32 ? R(a.x.thr_f[q][1]) : R(a.x.thr[q][1]);
+                        const int l = (xv[q] > t0) + (xv[q] > t1);
+                        level = l > level ? l : level;
+                    }
                 }
             }
             fl[k] = cs.fault ? uint8_t(0x82) : uint8_t(level);
@@ -514,6 +544,15 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
         acc[4] += (double)rsum[3];
         acc[5] += (double)rsum[4];
         acc[6] += (double)rsum[5];
+        if constexpr (EXT) {
+            // extension planes go out with this row (not deferred)
+            if (active) {
+                const long long off = (long long)y * nx + x0;
+#pragma unroll
+                for (int q = 0; q < kNumExt; ++q)
+                    if (a.x.plane[q] >= 0) store_pack<R, VEC>(sens + a.x.plane[q] * plane + off, xres[q]);
+            }
+        }
     }
     if (y0 < y1) store_row(y1 - 1);
     if (nfault) atomicAdd(faults, (unsigned long long)nfault);
@@ -533,7 +572,15 @@ static hipError_t launch_pass(int pass, const D2Q9Args& a, const void* fin, void
     const dim3 grid(a.g.nblocks), block(kBlock);
     switch (pass) {
     case kFused:
-        if (LKS_D2Q9_LDS_STAGE && StageGeom<S, VEC>::ok)
+        if (a.x.mask) {
+            // extension sensors: F32 and F64 storage, whose pieces always stage
+            if constexpr (std::is_same<S, float>::value || std::is_same<S, double>::value) {
+                if (!(LKS_D2Q9_LDS_STAGE && StageGeom<S, VEC>::ok)) return hipErrorInvalidValue;
+                d2q9_fused_lds<S, VEC, true><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        } else if (LKS_D2Q9_LDS_STAGE && StageGeom<S, VEC>::ok)
             d2q9_fused_lds<S, VEC><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
         else
             d2q9_kernel<S, VEC, kFused><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);

@@ -20,6 +20,24 @@ thread_local std::string g_create_err;
 
 int q_of(int lattice) { return lattice == LKS_D2Q9 ? 9 : (lattice == LKS_D2Q25 ? 25 : 0); }
 int nsens_of(int lattice) { return lattice == LKS_D2Q9 ? 3 : (lattice == LKS_D2Q25 ? 4 : 0); }
+
+// extension sensors: planes after the base planes, in increasing bit order
+lks::ExtArgs ext_args(const lks_config& c)
+{
+    lks::ExtArgs x;
+    x.mask = c.ext_mask;
+    int p = nsens_of(c.lattice);
+    for (int k = 0; k < lks::kNumExtHost; ++k) {
+        x.plane[k] = (c.ext_mask & (1u << k)) ? p++ : -1;
+        for (int j = 0; j < 2; ++j) {
+            x.thr[k][j] = c.thr_ext[k][j];
+            x.thr_f[k][j] = (float)c.thr_ext[k][j];
+        }
+    }
+    return x;
+}
+
+int planes_of(const lks_config& c) { return nsens_of(c.lattice) + __builtin_popcount(c.ext_mask); }
 size_t store_bytes(int dtype) { return dtype == LKS_F64 ? 8 : (dtype == LKS_F32 ? 4 : 2); }
 size_t sens_bytes(int dtype) { return dtype == LKS_F64 ? 8 : 4; }
 int wide_vec(int dtype) { return dtype == LKS_F64 ? 2 : 4; }
@@ -59,11 +77,21 @@ const char* validate_config(const lks_config* c)
     if (c->launch_vec != 0 && c->launch_vec != 1 && c->launch_vec != 2 && c->launch_vec != 4)
         return "launch_vec must be 0, 1, 2 or 4";
     if (c->dtype == LKS_F64 && c->launch_vec == 4) return "launch_vec 4 is not available for F64";
-    const unsigned valid = c->lattice == LKS_D2Q9 ? 7u : 15u;
-    if (c->flag_mask & ~valid) return "flag_mask names a sensor this lattice does not have";
+    if (c->ext_reserved != 0) return "ext_reserved must be 0";
+    const unsigned all_ext = (1u << LKS_MAX_EXT) - 1u;
+    const unsigned valid_ext = c->lattice == LKS_D2Q9 ? all_ext & ~(unsigned)LKS_X_QF
+                                                      : all_ext & ~(unsigned)(LKS_X_COMP | LKS_X_STRAIN);
+    if (c->ext_mask & ~valid_ext) return "ext_mask names a sensor this lattice does not have";
+    const unsigned valid = (c->lattice == LKS_D2Q9 ? 7u : 15u) | (c->ext_mask << 8);
+    if (c->flag_mask & ~valid) return "flag_mask names a sensor this configuration does not compute";
     for (int s = 0; s < LKS_MAX_SENSORS; ++s) {
         if (std::isnan(c->thr[s][0]) || std::isnan(c->thr[s][1])) return "threshold is NaN";
         if (c->thr[s][0] > c->thr[s][1]) return "thresholds must satisfy theta1 <= theta2";
+    }
+    for (int k = 0; k < LKS_MAX_EXT; ++k) {
+        if (!(c->ext_mask & (1u << k))) continue;
+        if (std::isnan(c->thr_ext[k][0]) || std::isnan(c->thr_ext[k][1])) return "threshold is NaN";
+        if (c->thr_ext[k][0] > c->thr_ext[k][1]) return "thresholds must satisfy theta1 <= theta2";
     }
     if (c->lattice == LKS_D2Q9) {
         if (c->bc_x != LKS_PERIODIC || c->bc_y != LKS_PERIODIC) return "D2Q9 grids are periodic";
@@ -93,6 +121,7 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
     a.rho0 = c.rho0;
     std::memcpy(a.thr, c.thr, sizeof(a.thr));
     a.mask = c.flag_mask;
+    a.x = ext_args(c);
     lks::d2q25_tile_shape(c.dtype, &a.tile_x, &a.tile_y);
     a.tiles_x = (c.nx + a.tile_x - 1) / a.tile_x;
     a.tiles_y = (c.ny + a.tile_y - 1) / a.tile_y;
@@ -172,6 +201,12 @@ size_t lks_scratch_bytes(const lks_config* cfg)
 
 int32_t lks_num_sensors(int32_t lattice) { return nsens_of(lattice); }
 
+int32_t lks_sensor_planes(const lks_config* cfg)
+{
+    if (validate_config(cfg)) return 0;
+    return planes_of(*cfg);
+}
+
 lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_stream, lks_ctx** out)
 {
     if (!out) return fail(nullptr, LKS_EINVAL, "out is NULL");
@@ -180,6 +215,8 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     if (!buf) return fail(nullptr, LKS_EINVAL, "buffers are NULL");
     if (cfg->lattice == LKS_D2Q25 && cfg->dtype != LKS_F32 && cfg->dtype != LKS_F64)
         return fail(nullptr, LKS_EUNSUPPORTED, "D2Q25 supports F32 and F64 storage");
+    if (cfg->ext_mask && cfg->dtype != LKS_F32 && cfg->dtype != LKS_F64)
+        return fail(nullptr, LKS_EUNSUPPORTED, "extension sensors need F32 or F64 storage");
     if (!buf->pop[0] || !buf->pop[1] || !buf->sensors || !buf->flags || !buf->sums || !buf->scratch)
         return fail(nullptr, LKS_EINVAL, "a buffer pointer is NULL");
     if (buf->pop[0] == buf->pop[1]) return fail(nullptr, LKS_EINVAL, "pop[0] and pop[1] alias");
@@ -200,7 +237,7 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     c->buf = *buf;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->Q = q_of(cfg->lattice);
-    c->nsens = nsens_of(cfg->lattice);
+    c->nsens = planes_of(*cfg);
     c->n = (long long)cfg->nx * cfg->ny;
     c->cur = 0;
     c->steps = 0;
@@ -228,6 +265,7 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     a.rho0_f = (float)cfg->rho0;
     for (int s = 0; s < LKS_MAX_SENSORS; ++s)
         for (int k = 0; k < 2; ++k) a.thr_f[s][k] = (float)cfg->thr[s][k];
+    a.x = ext_args(*cfg);
     c->a25 = d2q25_args(*cfg);
     c->nblocks = cfg->lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
     *out = c;
@@ -273,6 +311,8 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
     if (!c->ready) return fail(c, LKS_ESTATE, "step before init_equilibrium or restore");
     const bool q25 = c->cfg.lattice == LKS_D2Q25;
     if (q25 && !fused) return fail(c, LKS_EUNSUPPORTED, "the unfused passes exist for D2Q9 only");
+    if (c->cfg.ext_mask && !fused)
+        return fail(c, LKS_EUNSUPPORTED, "extension sensors are computed by the fused step only");
     const lks::D2Q9Args& a = c->a9;
     const int nb = c->nblocks;
     int done = 0;

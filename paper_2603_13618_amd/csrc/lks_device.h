@@ -73,6 +73,12 @@ __device__ __forceinline__ float pin_f32(float f)
     asm("" : "+v"(f));
     return f;
 }
+// the same barrier for any register-sized value (FP64 takes a register pair)
+template <typename T> __device__ __forceinline__ T pin(T v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)pin_f32(f)); }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
@@ -243,6 +249,89 @@ __device__ __forceinline__ R kl_phi(R x)
 // derivative phi'(x) = ln(1+x) (used by the adjoint seed)
 template <typename R>
 __device__ __forceinline__ R kl_dphi(R x) { return log1p_r(x); }
+
+// ---------------------------------------------------------------------------
+// Extended sensors: the rest of Table I on the f distribution, computed in
+// the same pass when a kernel is instantiated with them.  Order of the
+// values (and of the ABI's extension bits):
+//   0 Knudsen      sum |f^neq/f^eq|                      (eq. sensor-Knudsen-kin_f)
+//   1 relative H   |H(f) - H(f^eq)|, H = sum f ln(f/w)   (eq. Hneq-sensor)
+//   2 H dissipation   -sum Omega ln(f/w)                 (eq. Dissip-H-sensor)
+//   3 KL dissipation  -sum Omega ln(f/f^eq)              (eq. Dissip-HKL-sensor)
+//   4 entropic estimate |2 - alpha_f|, printed polynomial (eqs. alpha-polynomial-1/2)
+//   5 rate of shear |(1/mu)[(tr P/D) I - P]|             (eq. sensor-S-kin)
+//   6 viscous heating |u . P|                             (eq. sensor-qH-kin)
+//   7 Fourier flux |q^neq - u . P| (D2Q25)               (eq. sensor-qF-kin-ryk, g = 0)
+//   8 rate of compression sqrt(D)|tr P|/(2 mu) (D2Q9, lambda = 0)   (eq. sensor-C-kin)
+//   9 rate of strain |P|/(2 mu) (D2Q9, lambda = 0)      (eq. sensor-E-kin)
+// with Omega_i = -(f_i - f^eq_i)/tau (BGK), P = sum v v f^neq.
+// Cancellation-free forms (sum_i f^neq_i = 0 because f^eq carries the cell's
+// own mass): H(f) - H(f^eq) = S_KL + sum f^neq ln(f^eq/w) and
+// -sum Omega ln(f/w) = (1/tau) [sum f^neq ln(1 + x) + sum f^neq ln(f^eq/w)],
+// x = f^neq/f^eq; 2 - alpha is evaluated directly, not as a difference.
+// ---------------------------------------------------------------------------
+constexpr int kNumExt = 10;
+
+template <typename R> struct ExtAcc {
+    R kn = R(0), L = R(0), shkl = R(0), a1 = R(0), a2 = R(0), a3 = R(0), a4 = R(0);
+    // one population: its non-equilibrium part, x = fneq/feq, f itself and
+    // ln(f^eq/w)
+    __device__ __forceinline__ void add(R fneq, R x, R f, R ln_feq_w)
+    {
+        kn += fabs(x);
+        L += fneq * ln_feq_w;
+        shkl += fneq * log1p_r(x);
+        const R y = fneq * rcp(f);             // f^neq / f
+        const R t1 = fneq * y, t2 = t1 * y, t3 = t2 * y;
+        a1 += t1;
+        a2 += t2;
+        a3 += t3;
+        a4 += t3 * y;
+    }
+};
+
+// Finish the extended sensors of one cell.  kl = S_KL, inv_tau = 1/tau,
+// inv_mu = 1/mu; P components, velocity and (D2Q25) q^neq; d2q25 selects the
+// lattice-specific entries (Fourier flux there, compression and strain on
+// D2Q9).  A positivity fault makes the five log/ratio sensors +inf.  The
+// stress components are taken through pin() so that no product here is
+// shared with the base sensors' arithmetic (which would change how the
+// compiler contracts S_PI and make it differ by an ulp with the extension on).
+template <typename R>
+__device__ __forceinline__ void ext_finish(const ExtAcc<R>& e, R kl, bool fault, R inv_tau, R inv_mu,
+                                           R pxx_, R pxy_, R pyy_, R ux, R uy, R qx, R qy, bool d2q25,
+                                           R (&out)[kNumExt])
+{
+    const R pxx = pin(pxx_), pxy = pin(pxy_), pyy = pin(pyy_);
+    const R inf = R(INFINITY);
+    out[0] = fault ? inf : e.kn;
+    out[1] = fault ? inf : fabs(kl + e.L);
+    out[2] = fault ? inf : inv_tau * (e.shkl + e.L);
+    out[3] = fault ? inf : inv_tau * e.shkl;
+    // a_n = (-1)^(n-1) / (n(n+1)) sum f^neq^(n+1) / f^n
+    R dev = R(0);
+    if (e.a1 != R(0)) {
+        const R ia1 = rcp(R(0.5) * e.a1);
+        const R r2 = R(-1.0 / 6.0) * e.a2 * ia1, r3 = R(1.0 / 12.0) * e.a3 * ia1,
+                r4 = R(-1.0 / 20.0) * e.a4 * ia1;
+        dev = R(4) * r2 - R(16) * r2 * r2 + R(8) * r3 - R(80) * r2 * r3 + R(80) * r2 * r2 * r2 + R(16) * r4;
+    }
+    out[4] = fault ? inf : fabs(dev);
+    const R dxy = pxx - pyy;
+    out[5] = inv_mu * sqrt(R(0.5) * dxy * dxy + R(2) * pxy * pxy);
+    const R hx = ux * pxx + uy * pxy, hy = ux * pxy + uy * pyy;
+    out[6] = sqrt(hx * hx + hy * hy);
+    if (d2q25) {
+        const R fx = qx - hx, fy = qy - hy;
+        out[7] = sqrt(fx * fx + fy * fy);
+        out[8] = R(0);
+        out[9] = R(0);
+    } else {
+        out[7] = R(0);
+        out[8] = R(0.70710678118654752) * fabs(pxx + pyy) * inv_mu;      // sqrt(2) |tr P| / (2 mu)
+        out[9] = R(0.5) * inv_mu * sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Explicit waits for kernels that stage through LDS with direct global->LDS

@@ -19,6 +19,18 @@ struct GridShape {
     int nblocks;
 };
 
+constexpr int kNumExtHost = 10;    // extension sensors (LKS_MAX_EXT)
+constexpr int kExtFlagShift = 8;   // flag_mask bit of extension sensor k: 8 + k
+
+// Extension sensors of a launch: which are computed, where they are stored,
+// and the thresholds of those that drive the flags.
+struct ExtArgs {
+    unsigned mask;                   // 0 = none (the kernels without them run)
+    int plane[kNumExtHost];          // sensor plane of sensor k, -1 = not stored
+    double thr[kNumExtHost][2];
+    float thr_f[kNumExtHost][2];     // the same rounded to FP32
+};
+
 struct D2Q9Args {
     int nx, ny;
     long long plane;          // nx * ny
@@ -31,6 +43,7 @@ struct D2Q9Args {
     // them in scalar registers
     float inv_tau_f, rho0_f;
     float thr_f[4][2];
+    ExtArgs x;
 };
 
 struct D2Q25Args {
@@ -44,6 +57,7 @@ struct D2Q25Args {
     int tile_x, tile_y;       // cells per workgroup tile
     int tiles_x, tiles_y;
     int nblocks;
+    ExtArgs x;
 };
 
 // D2Q9 passes: the fused step and the three passes of the unfused baseline

@@ -20,6 +20,27 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 PERIODIC, OUTFLOW = 0, 1
 S_KL, S_NEQ, S_PI, S_Q = 1, 2, 4, 8
 NSUMS = 8
+# extension sensors (bit k of ext_mask; flag_mask bit 8 + k), plane order
+EXT_NAMES = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf", "comp", "strain")
+MAX_EXT = len(EXT_NAMES)
+
+
+def flag_x(k):
+    """flag_mask bit of extension sensor k (an index or a name)."""
+    k = EXT_NAMES.index(k) if isinstance(k, str) else int(k)
+    return 1 << (8 + k)
+
+
+def ext_mask_of(ext):
+    """ext_mask from an int mask or an iterable of names / indices."""
+    if ext is None:
+        return 0
+    if isinstance(ext, int):
+        return ext
+    m = 0
+    for k in ext:
+        m |= 1 << (EXT_NAMES.index(k) if isinstance(k, str) else int(k))
+    return m
 STATUS = {0: "LKS_OK", 1: "LKS_EINVAL", 2: "LKS_ESTATE", 3: "LKS_EHIP", 4: "LKS_ENONPOS",
           5: "LKS_ENAN", 6: "LKS_EUNSUPPORTED"}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
@@ -39,7 +60,8 @@ class Config(ctypes.Structure):
                 ("dx", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("flag_mask", ctypes.c_uint32), ("launch_rows", ctypes.c_int32),
                 ("thr", (ctypes.c_double * 2) * 4), ("max_steps", ctypes.c_int32),
-                ("launch_vec", ctypes.c_int32)]
+                ("launch_vec", ctypes.c_int32), ("ext_mask", ctypes.c_uint32),
+                ("ext_reserved", ctypes.c_int32), ("thr_ext", (ctypes.c_double * 2) * MAX_EXT)]
 
 
 class Buffers(ctypes.Structure):
@@ -62,6 +84,7 @@ def lib():
         sig = {
             "lks_scratch_bytes": ([ctypes.POINTER(Config)], ctypes.c_size_t),
             "lks_num_sensors": ([I32], I32),
+            "lks_sensor_planes": ([ctypes.POINTER(Config)], I32),
             "lks_create": ([ctypes.POINTER(Config), ctypes.POINTER(Buffers), P, ctypes.POINTER(P)], I32),
             "lks_init_equilibrium": ([P, P, P, P, P], I32),
             "lks_restore": ([P, I32, I64], I32),
@@ -97,7 +120,7 @@ def _stream_handle(device):
 
 def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                 bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
-                launch_rows=0, launch_vec=0):
+                launch_rows=0, launch_vec=0, ext=None, thr_ext=None):
     c = Config()
     c.lattice, c.nx, c.ny = lattice, nx, ny
     c.dtype = DTYPES[dtype] if isinstance(dtype, str) else dtype
@@ -110,6 +133,12 @@ def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, 
         c.thr[s][0], c.thr[s][1] = float(t[s, 0]), float(t[s, 1])
     c.max_steps = max_steps
     c.launch_vec = launch_vec
+    c.ext_mask = ext_mask_of(ext)
+    c.ext_reserved = 0
+    te = (np.full((MAX_EXT, 2), math.inf) if thr_ext is None
+          else np.asarray(thr_ext, np.float64).reshape(MAX_EXT, 2))
+    for k in range(MAX_EXT):
+        c.thr_ext[k][0], c.thr_ext[k][1] = float(te[k, 0]), float(te[k, 1])
     return c
 
 
@@ -126,20 +155,26 @@ def _check(status, ctx=None):
 class Lattice:
     """One simulation context with torch-owned device buffers.
 
-    Attributes: pop (2 tensors [Q, ny, nx]), sensors [nsens, ny, nx],
-    flags [ny, nx] uint8, sums [max_steps, 8] float64.
+    Attributes: pop (2 tensors [Q, ny, nx]), sensors [nsens, ny, nx] (the
+    base sensors, then one plane per extension sensor in ext, in EXT_NAMES
+    order), flags [ny, nx] uint8, sums [max_steps, 8] float64.
+    ext: extension sensors (names from EXT_NAMES, indices or a bit mask);
+    thr_ext: [MAX_EXT, 2] thresholds, used for sensors whose flag_x bit is in
+    flag_mask.
     """
 
     def __init__(self, lattice=D2Q9, nx=64, ny=64, dtype="f32", tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                  bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
-                 launch_rows=0, launch_vec=0, device="cuda"):
+                 launch_rows=0, launch_vec=0, ext=None, thr_ext=None, device="cuda"):
         self.device = torch.device(device)
         self.cfg = make_config(lattice, nx, ny, dtype, tau, mu, dt, dx, bc, rho0, thr, flag_mask,
-                               max_steps, launch_rows, launch_vec)
+                               max_steps, launch_rows, launch_vec, ext, thr_ext)
         self.Q = lattice
         self.nx, self.ny = nx, ny
         self.dtype = self.cfg.dtype
-        nsens = int(lib().lks_num_sensors(lattice))
+        nsens = int(lib().lks_sensor_planes(ctypes.byref(self.cfg))) or \
+            int(lib().lks_num_sensors(lattice))
+        self.ext_mask = self.cfg.ext_mask
         sdt = torch.float64 if self.dtype == F64 else torch.float32
         tdt = _TORCH_STORE[self.dtype]
         dev = self.device
@@ -163,6 +198,14 @@ class Lattice:
         st = lib().lks_create(ctypes.byref(self.cfg), ctypes.byref(self.buf),
                               _stream_handle(dev), ctypes.byref(self.ctx))
         _check(st, None)
+
+    def ext(self, name):
+        """The sensor plane of extension sensor `name` (must be in ext)."""
+        k = EXT_NAMES.index(name)
+        if not self.ext_mask & (1 << k):
+            raise KeyError(name)
+        base = int(lib().lks_num_sensors(self.Q))
+        return self.sensors[base + bin(self.ext_mask & ((1 << k) - 1)).count("1")]
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)

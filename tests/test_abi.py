@@ -4,6 +4,7 @@ import ctypes
 import glob
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -52,11 +53,47 @@ def test_config_validation_on_host():
     assert L.lks_status_str(4) == b"non-positive populations"
 
 
-def test_abi_struct_layout_matches_header():
-    # offsets of the ctypes mirror against the C declaration order/alignment
-    assert ctypes.sizeof(lks.Config) == 4 * 6 + 8 * 5 + 4 + 4 + 8 * 8 + 4 + 4
-    assert lks.Config.thr.offset == 72
-    assert ctypes.sizeof(lks.Buffers) == 8 * 7
+def test_abi_struct_layout_matches_header(tmp_path):
+    # sizes and offsets of the ctypes mirror against what the C compiler makes
+    # of include/lks.h
+    fields = ["lattice", "nx", "dtype", "tau", "rho0", "flag_mask", "launch_rows", "thr",
+              "max_steps", "launch_vec", "ext_mask", "ext_reserved", "thr_ext"]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lks.h\"\nint main(void){\n"
+                   + 'printf("%zu %zu", sizeof(lks_config), sizeof(lks_buffers));\n'
+                   + "".join(f'printf(" %zu", offsetof(lks_config, {f}));\n' for f in fields)
+                   + 'printf(" %zu %zu\\n", offsetof(lks_buffers, sensors), offsetof(lks_buffers, scratch_bytes));'
+                   + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(lks.Config), ctypes.sizeof(lks.Buffers)]
+    want += [getattr(lks.Config, f).offset for f in fields]
+    want += [lks.Buffers.sensors.offset, lks.Buffers.scratch_bytes.offset]
+    assert got == want
+
+
+def test_extension_sensor_validation_on_host():
+    L = lks.lib()
+    c9 = lks.make_config(9, 64, 64, "f32", tau=0.6, ext=["kn", "shear", "strain"],
+                         flag_mask=1 | lks.flag_x("shear"))
+    assert lks.scratch_bytes(c9) > 0
+    assert L.lks_sensor_planes(ctypes.byref(c9)) == 3 + 3
+    c25 = lks.make_config(25, 64, 64, "f32", mu=1e-3, dt=1e-3, dx=0.1, ext=["qf", "alpha"])
+    assert L.lks_sensor_planes(ctypes.byref(c25)) == 4 + 2
+    bad = [lks.make_config(9, 64, 64, "f32", tau=0.6, ext=["qf"]),              # no energy flux
+           lks.make_config(25, 64, 64, "f32", mu=1e-3, dt=1e-3, dx=0.1, ext=["comp"]),
+           lks.make_config(9, 64, 64, "f32", tau=0.6, ext=["kn"], flag_mask=lks.flag_x("hr")),
+           lks.make_config(9, 64, 64, "f32", tau=0.6, ext=1 << 10),
+           lks.make_config(9, 64, 64, "f32", tau=0.6, ext=["kn"],
+                           thr_ext=[[2.0, 1.0]] + [[0.0, 0.0]] * 9)]
+    for c in bad:
+        assert lks.scratch_bytes(c) == 0 and L.lks_sensor_planes(ctypes.byref(c)) == 0
+    r = lks.make_config(9, 64, 64, "f32", tau=0.6)
+    r.ext_reserved = 1
+    assert lks.scratch_bytes(r) == 0
 
 
 @pytest.mark.parametrize("name", ["lks_step", "lks_moments", "lks_check", "lks_init_equilibrium"])

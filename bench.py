@@ -31,7 +31,7 @@ BYTES_F32_PLAIN = 193           # stream 36 + 36, sensors 36 + 13, collide 36 + 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2q9_fused_f32_4096.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_13618_amd", "csrc", "d2q9.hip")
 # the fused FP32 step at the default launch shape (4 cells per thread)
-FUSED_KERNEL = "d2q9_fused_lds<float,4>"
+FUSED_KERNEL = "d2q9_fused_lds<float,4,false>"
 FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 
 
@@ -44,9 +44,12 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=40)
     p.add_argument("--forms", action="store_true",
                    help="also time the BF16/FP16 storage forms on the 8192^2 workload")
+    p.add_argument("--ext", action="store_true",
+                   help="also time the fused steps with every extension sensor on")
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
     p.add_argument("--workload", choices=["smooth4096", "riemann2048", "smooth8192-bf16",
-                                          "smooth8192-f16", "adjoint1024"],
+                                          "smooth8192-f16", "adjoint1024", "smooth4096-ext",
+                                          "riemann2048-ext"],
                    default="smooth4096", help="workload of --mode kernel (profiling runs)")
     p.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                    help="assemble the traffic summary from four rocprofv3 --pmc output "
@@ -271,6 +274,8 @@ def main():
 
     if args.forms:
         out["forms"] = time_forms(torch, lks, inputs, workloads, dev, ev)
+    if args.ext:
+        out["ext"] = time_ext(torch, lks, inputs, workloads, dev, ev)
 
     del lat
     torch.cuda.empty_cache()
@@ -301,9 +306,61 @@ def copy_ceiling(torch, lks, dev, ev, nbytes):
     return 2 * nbytes / t / 1e9
 
 
+EXT9 = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "comp", "strain")
+EXT25 = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf")
+
+
+def ext_lattices(lks, inputs, workloads, dev, steps):
+    """The two extension-sensor workloads, initialised: D2Q9 4096^2 FP32 with
+    every D2Q9 extension sensor, D2Q25 2048^2 FP32 Riemann with every D2Q25
+    one (thresholds as the base workloads, extension sensors not flagged)."""
+    wl = workloads.SMOOTH_4096
+    n = wl["nx"]
+    rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+    a = lks.Lattice(9, n, n, "f32", tau=wl["tau"], thr=wl["thr"], flag_mask=wl["flag_mask"],
+                    max_steps=max(steps, 1), ext=EXT9, device=dev)
+    a.init(rho, ux, uy)
+    wq = workloads.RIEMANN_2048
+    m = wq["nx"]
+    rho, ux, uy, T, states = inputs.riemann_quadrants(m, seed=wq["seed"])
+    dx = 1.0 / m
+    b = lks.Lattice(25, m, m, "f32", mu=wq["mu"], dt=inputs.riemann_dt(states, dx), dx=dx,
+                    bc=(1, 1), thr=wq["thr"], flag_mask=wq["flag_mask"], max_steps=max(steps, 1),
+                    ext=EXT25, device=dev)
+    b.init(rho, ux, uy, T)
+    return a, b
+
+
+def time_ext(torch, lks, inputs, workloads, dev, ev):
+    """Fused steps with every extension sensor on (timing only)."""
+    k = 40
+    a, b = ext_lattices(lks, inputs, workloads, dev, k)
+    res = {}
+    for name, lat, nbytes in (("d2q9_4096_f32_ext9", a, 85 + 4 * len(EXT9)),
+                              ("d2q25_2048_f32_ext8", b, 217 + 4 * len(EXT25))):
+        lat.step(3)
+        torch.cuda.synchronize()
+        s, e = ev(), ev()
+        s.record()
+        lat.step(k)
+        e.record()
+        torch.cuda.synchronize()
+        t = s.elapsed_time(e) / k * 1e-3
+        cells = lat.nx * lat.ny
+        res[name] = {"MLUPS": round(cells / t / 1e6, 1), "us_per_step": round(t * 1e6, 1),
+                     "GBps_model": round(nbytes * cells / t / 1e9, 1), "bytes_per_lup": nbytes,
+                     "faults": lat.check()}
+    del a, b
+    torch.cuda.empty_cache()
+    return res
+
+
 def kernel_only(args, torch, lks, inputs, workloads, dev):
     """A short run of one of the other workloads (for profilers)."""
-    if args.workload == "riemann2048":
+    if args.workload.endswith("-ext"):
+        a, b = ext_lattices(lks, inputs, workloads, dev, args.steps)
+        (a if args.workload.startswith("smooth") else b).step(args.steps)
+    elif args.workload == "riemann2048":
         wl = workloads.RIEMANN_2048
         n = wl["nx"]
         rho, ux, uy, T, states = inputs.riemann_quadrants(n, seed=wl["seed"])

@@ -277,7 +277,6 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
     R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0), qy = R(0);
     R xmin = R(0), xmax = R(0), feqmin = R(0);
     bool first = true;
-    ExtAcc<R> xa;
     const long long off = (long long)Y * nx + X;
     d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
         const int i = 5 * ia + ib;
@@ -286,11 +285,6 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
         const R fneq = d - deq;
         const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
         const R x = fneq * rcp(feq);
-        if constexpr (EXT) {
-            // ln(f^eq/w) = ln(rho0 + deq/w); f = w rho0 + d
-            const R lq = log1p_r((rho0 - R(1)) + deq * R(1.0 / (gh5_w(ia) * gh5_w(ib))));
-            xa.add(fneq, x, R(gh5_w(ia) * gh5_w(ib)) * rho0 + d, lq);
-        }
         kl += (fneq * x) * kl_series(x);           // series branch; fallback below
         xmin = first ? x : fmin(xmin, x);
         xmax = first ? fabs(x) : fmax(xmax, fabs(x));
@@ -345,11 +339,27 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
             }
         }
         if constexpr (EXT) {
+            // A separate pass on opaque copies (pin) of the moments and of the
+            // staged populations, after the base arithmetic: no base expression
+            // gains a use, so the base results do not depend on the extension.
+            const R drho_p = pin(drho), rho_p = pin(rho), ux_p = pin(ux), uy_p = pin(uy),
+                    tm1_p = pin(tm1), rho0_p = pin(rho0);
+            ExtAcc<R> xa;
+            const ExtNeed need(a.x.mask);
+            d2q25_deq<R>(drho_p, rho_p, ux_p, uy_p, tm1_p, [&](int ia, int ib, R deq) {
+                const R d = pin(lds[(5 * ia + ib) * T::kPlane + rb[2] + tx]);
+                const R w = R(gh5_w(ia) * gh5_w(ib));
+                const R fneq = d - deq;
+                const R x = fneq * rcp(w * rho0_p + deq);
+                // f = w rho0 + d; f^eq/w - 1 = (rho0 - 1) + deq/w
+                xa.add(need, fneq, x, w * rho0_p + d,
+                       (rho0_p - R(1)) + deq * R(1.0 / (gh5_w(ia) * gh5_w(ib))));
+            });
             // tau = mu/(rho T), the configured mu
             R xv[kNumExt];
             const R inv_mu = R(1.0 / a.mu);
-            ext_finish<R>(xa, kl, fault, rho * (R(1) + tm1) * inv_mu, inv_mu, pxx, pxy, pyy, ux, uy,
-                          qx, qy, true, xv);
+            ext_finish<R>(xa, pin(kl), fault, rho_p * (R(1) + tm1_p) * inv_mu, inv_mu, pxx, pxy, pyy,
+                          ux_p, uy_p, pin(qx), pin(qy), true, xv);
 #pragma unroll
             for (int q = 0; q < kNumExt; ++q) {
                 if (a.x.plane[q] >= 0) sens[a.x.plane[q] * plane + off] = xv[q];

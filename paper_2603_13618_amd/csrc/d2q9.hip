@@ -85,7 +85,8 @@ template <typename R> struct CellSense {
 // isothermal lattice).
 template <typename R, bool SENSE, bool COLLIDE, bool EXT = false>
 __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau, R& drho_out,
-                                                    R& jx_out, R& jy_out, R* ext = nullptr)
+                                                    R& jx_out, R& jy_out, R* ext = nullptr,
+                                                    unsigned ext_mask = 0)
 {
     // moments of the deviation form: rho - rho0 = sum d, j = sum c d
     const R drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
@@ -124,17 +125,11 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
     if constexpr (SENSE) {
         R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
         R xmax = R(0), xmin = R(0), feqmin = R(0);
-        ExtAcc<R> xa;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const R fneq = d[i] - deq[i];
             const R feq = w9<R>(i) * rho0 + deq[i];
             const R x = fneq * rcp(feq);
-            if constexpr (EXT) {
-                // ln(f^eq/w) = ln(rho0 + deq/w); f = w rho0 + d
-                const R lq = log1p_r((rho0 - R(1)) + deq[i] * R(1.0 / w9<double>(i)));
-                xa.add(fneq, x, w9<R>(i) * rho0 + d[i], lq);
-            }
             // S_KL term feq phi(x) = fneq x p(x) on the series branch
             kl += (fneq * x) * kl_series(x);
             xmax = i == 0 ? fabs(x) : fmax(xmax, fabs(x));
@@ -158,12 +153,45 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
         out.neq = neq;
         out.pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
         if constexpr (EXT) {
+            // The extension sensors work on opaque copies (pin) of the
+            // pre-collision deviations, their equilibrium parts and the
+            // base quantities they need, and run after the collision: no
+            // base expression gains a use and the base arithmetic stays in
+            // one block, so its results do not depend on the extension.
+            R dp[9], qp[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                dp[i] = pin(d[i]);
+                qp[i] = pin(deq[i]);
+            }
+            const R kl_p = pin(kl), rho0_p = pin(rho0), tau_p = pin(inv_tau), irho_p = pin(irho);
+            const R ux_p = pin(ux), uy_p = pin(uy);
+            const R pxx_p = pin(pxx), pxy_p = pin(pxy), pyy_p = pin(pyy);
+            const bool fault = out.fault;
+            if constexpr (COLLIDE) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) d[i] -= inv_tau * (d[i] - deq[i]);
+            }
+            ExtAcc<R> xa;
+            const ExtNeed need(ext_mask);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R fneq = dp[i] - qp[i];
+                const R x = fneq * rcp(w9<R>(i) * rho0_p + qp[i]);
+                // f = w rho0 + d; f^eq/w - 1 = (rho0 - 1) + deq/w
+                xa.add(need, fneq, x, w9<R>(i) * rho0_p + dp[i],
+                       (rho0_p - R(1)) + qp[i] * R(1.0 / w9<double>(i)));
+            }
             R xv[kNumExt];
-            const R inv_mu = R(3) * inv_tau * irho;          // mu = tau rho / 3
-            ext_finish<R>(xa, kl, out.fault, inv_tau, inv_mu, pxx, pxy, pyy, ux, uy, R(0), R(0),
+            const R inv_mu = R(3) * tau_p * irho_p;          // mu = tau rho / 3
+            ext_finish<R>(xa, kl_p, fault, tau_p, inv_mu, pxx_p, pxy_p, pyy_p, ux_p, uy_p, R(0), R(0),
                           false, xv);
 #pragma unroll
             for (int k = 0; k < kNumExt; ++k) ext[k] = xv[k];
+            drho_out = drho;
+            jx_out = jx;
+            jy_out = jy;
+            return out;
         }
     }
     if constexpr (COLLIDE) {
@@ -434,6 +462,7 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     R res[9][VEC];
     R s_kl[VEC], s_neq[VEC], s_pi[VEC];
     uint8_t fl[VEC];
+    R xres[EXT ? kNumExt : 1][VEC];
     auto store_row = [&](int y) {
         if (active) {
             const long long off = (long long)y * nx + x0;
@@ -443,6 +472,11 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             store_pack<R, VEC>(sens + plane + off, s_neq);
             store_pack<R, VEC>(sens + 2 * plane + off, s_pi);
             store_pack<uint8_t, VEC>(flags + off, fl);
+            if constexpr (EXT) {
+#pragma unroll
+                for (int q = 0; q < kNumExt; ++q)
+                    if (a.x.plane[q] >= 0) store_pack<R, VEC>(sens + a.x.plane[q] * plane + off, xres[q]);
+            }
         }
     };
 
@@ -491,7 +525,6 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
         if (y > y0) store_row(y - 1);
 
         R rsum[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-        R xres[EXT ? kNumExt : 1][VEC];
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
             R dc[9];
@@ -500,7 +533,8 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             R drho, jx, jy;
             R xv[kNumExt];
             LKS_CELL_BARRIER();
-            const CellSense<R> cs = cell_update<R, true, true, EXT>(dc, rho0, inv_tau, drho, jx, jy, xv);
+            const CellSense<R> cs = cell_update<R, true, true, EXT>(dc, rho0, inv_tau, drho, jx, jy, xv,
+                                                                    a.x.mask);
 #pragma unroll
             for (int i = 0; i < 9; ++i) res[i][k] = dc[i];
             int level = 0;
@@ -544,15 +578,6 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
         acc[4] += (double)rsum[3];
         acc[5] += (double)rsum[4];
         acc[6] += (double)rsum[5];
-        if constexpr (EXT) {
-            // extension planes go out with this row (not deferred)
-            if (active) {
-                const long long off = (long long)y * nx + x0;
-#pragma unroll
-                for (int q = 0; q < kNumExt; ++q)
-                    if (a.x.plane[q] >= 0) store_pack<R, VEC>(sens + a.x.plane[q] * plane + off, xres[q]);
-            }
-        }
     }
     if (y0 < y1) store_row(y1 - 1);
     if (nfault) atomicAdd(faults, (unsigned long long)nfault);

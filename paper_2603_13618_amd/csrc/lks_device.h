@@ -272,21 +272,55 @@ __device__ __forceinline__ R kl_dphi(R x) { return log1p_r(x); }
 // ---------------------------------------------------------------------------
 constexpr int kNumExt = 10;
 
+// ln(1 + t) for the extension sensors.  FP32: ln(1 + t) = 2 atanh(u),
+// u = t / (2 + t), as the odd series to u^11 for t in [-0.4, 0.5] (|u| <= 1/4,
+// relative truncation u^12 / 13 < 5e-9, one reciprocal and six FMAs), else the
+// hardware base-2 logarithm of 1 + t (ln is not small there, so its absolute
+// accuracy suffices).  FP64: the library log1p.
+__device__ __forceinline__ float ln1p_fast(float t)
+{
+    const float u = t * rcp(2.0f + t);
+    const float u2 = u * u;
+    float p = 2.0f / 11.0f;
+    p = p * u2 + 2.0f / 9.0f;
+    p = p * u2 + 2.0f / 7.0f;
+    p = p * u2 + 2.0f / 5.0f;
+    p = p * u2 + 2.0f / 3.0f;
+    p = p * u2 + 2.0f;
+    const float direct = __builtin_amdgcn_logf(1.0f + t) * 0.69314718055994531f;
+    return (t >= -0.4f && t <= 0.5f) ? u * p : direct;
+}
+__device__ __forceinline__ double ln1p_fast(double t) { return log1p(t); }
+
+// which of the costly per-population sums a launch needs (wave-uniform, so
+// the guards are scalar branches): the sum of f^neq ln(f^eq/w) (relative H,
+// H dissipation), of f^neq ln(1 + x) (both dissipations), the alpha moments
+struct ExtNeed {
+    bool L, S, A;
+    __device__ __forceinline__ explicit ExtNeed(unsigned m)
+        : L(m & 0x6u), S(m & 0xCu), A(m & 0x10u) {}
+};
+
 template <typename R> struct ExtAcc {
     R kn = R(0), L = R(0), shkl = R(0), a1 = R(0), a2 = R(0), a3 = R(0), a4 = R(0);
     // one population: its non-equilibrium part, x = fneq/feq, f itself and
-    // ln(f^eq/w)
-    __device__ __forceinline__ void add(R fneq, R x, R f, R ln_feq_w)
+    // t = f^eq/w - 1
+    // The inputs are taken through pin() so that nothing computed here is
+    // shared with (and changes the contraction of) the base arithmetic.
+    __device__ __forceinline__ void add(const ExtNeed& need, R fneq_, R x_, R f_, R t_)
     {
+        const R fneq = pin(fneq_), x = pin(x_), f = pin(f_), t = pin(t_);
         kn += fabs(x);
-        L += fneq * ln_feq_w;
-        shkl += fneq * log1p_r(x);
-        const R y = fneq * rcp(f);             // f^neq / f
-        const R t1 = fneq * y, t2 = t1 * y, t3 = t2 * y;
-        a1 += t1;
-        a2 += t2;
-        a3 += t3;
-        a4 += t3 * y;
+        if (need.L) L += fneq * ln1p_fast(t);
+        if (need.S) shkl += fneq * ln1p_fast(x);
+        if (need.A) {
+            const R y = fneq * rcp(f);             // f^neq / f
+            const R t1 = fneq * y, t2 = t1 * y, t3 = t2 * y;
+            a1 += t1;
+            a2 += t2;
+            a3 += t3;
+            a4 += t3 * y;
+        }
     }
 };
 

@@ -230,6 +230,46 @@ const char* lks_status_str(lks_status s);
  * when ctx is NULL); valid until the next call on the same context. */
 const char* lks_last_error(const lks_ctx* ctx);
 
+/* ---- Regridding hand-off (Sec. II.B.2, regridding steps 1-2) ----
+ * The flag map is turned into refinement patches in three calls: a buffer
+ * layer around the tagged cells (the paper uses two buffer cells, Sec. IV),
+ * tag counts on blocking-factor tiles, and Berger-Rigoutsos clustering of the
+ * tagged tiles into rectangles of a minimum grid efficiency (98 % in 2D in
+ * the paper).  The first two run on the device on the context's stream; the
+ * clustering runs on the host on the (small) tile counts. */
+#define LKS_MAX_BUFFER 8
+
+typedef struct {
+    int32_t x0, y0, x1, y1;   /* cells [x0, x1) x [y0, y1) */
+} lks_box;
+
+/* Buffer layer: levels[c] = max over the (2b+1) x (2b+1) square around c of
+ * (flags & 3), ghost cells by the context's boundary conditions (periodic:
+ * wrap; outflow: the edge cell repeated).  flags, levels: device [ny][nx]
+ * uint8 (they must not alias; flags may be the context's own flag buffer).
+ * 0 <= b <= LKS_MAX_BUFFER, else LKS_EINVAL. */
+lks_status lks_tag_buffer(lks_ctx* ctx, int32_t b, const uint8_t* flags, uint8_t* levels);
+
+/* Tile counts: counts[t] = number of cells with (levels & 3) >= level in
+ * tile t of ts x ts cells, tiles row-major [ceil(ny/ts)][ceil(nx/ts)] (the
+ * high-edge tiles may be partial).  levels: device [ny][nx] uint8; counts:
+ * device int32.  1 <= ts <= 64, 1 <= level <= 2, else LKS_EINVAL. */
+lks_status lks_tag_tiles(lks_ctx* ctx, const uint8_t* levels, int32_t level, int32_t ts,
+                         int32_t* counts);
+
+/* Berger-Rigoutsos clustering (host): counts is a host array as written by
+ * lks_tag_tiles for an nx x ny grid and tile size ts.  Boxes are tight
+ * bounding boxes of tagged tiles, aligned to the tiles (clipped to the grid),
+ * disjoint, covering every tagged tile, each with tagged cells >= eff x cells
+ * unless no cut leaving min_tiles tiles on both sides exists.  Cuts: a hole
+ * of a signature nearest the middle, else the strongest inflection of its
+ * Laplacian, else halfway along the longer side (ties: x before y, lower
+ * index).  Writes up to max_boxes boxes (depth-first order) and sets *nboxes
+ * to the number found; LKS_EINVAL if that exceeds max_boxes or an argument
+ * is invalid. */
+lks_status lks_cluster(const int32_t* counts, int32_t nx, int32_t ny, int32_t ts, double eff,
+                       int32_t min_tiles, lks_box* boxes, int32_t max_boxes, int32_t* nboxes);
+
 /* Plain device-to-device copy of bytes (multiple of 16, 16-B aligned
  * pointers) on hip_stream: the bandwidth yardstick used to calibrate traffic
  * counters and the attainable HBM rate. */

@@ -419,6 +419,28 @@ lks_status lks_check(lks_ctx* c, int64_t* n_nonpos)
     return LKS_OK;
 }
 
+lks_status lks_tag_buffer(lks_ctx* c, int32_t b, const uint8_t* flags, uint8_t* levels)
+{
+    if (!c) return LKS_EINVAL;
+    if (!flags || !levels) return fail(c, LKS_EINVAL, "flags or levels is NULL");
+    if (flags == levels) return fail(c, LKS_EINVAL, "flags and levels must not alias");
+    if (b < 0 || b > lks::kMaxBuffer) return fail(c, LKS_EINVAL, "buffer width out of range");
+    return hip_check(c, lks::launch_tag_buffer(flags, levels, c->cfg.nx, c->cfg.ny, c->cfg.bc_x,
+                                                c->cfg.bc_y, b, c->stream),
+                      "tag buffer");
+}
+
+lks_status lks_tag_tiles(lks_ctx* c, const uint8_t* levels, int32_t level, int32_t ts, int32_t* counts)
+{
+    if (!c) return LKS_EINVAL;
+    if (!levels || !counts) return fail(c, LKS_EINVAL, "levels or counts is NULL");
+    if (ts < 1 || ts > 64) return fail(c, LKS_EINVAL, "tile size must be 1 .. 64");
+    if (level < 1 || level > 2) return fail(c, LKS_EINVAL, "level must be 1 or 2");
+    if (!aligned(counts, 4)) return fail(c, LKS_EINVAL, "counts misaligned");
+    return hip_check(c, lks::launch_tag_tiles(levels, counts, c->cfg.nx, c->cfg.ny, level, ts, c->stream),
+                      "tag tiles");
+}
+
 lks_status lks_step_from(lks_ctx* c, const void* src, void* dst)
 {
     if (!c) return LKS_EINVAL;

@@ -104,6 +104,13 @@ hipError_t launch_adj_init(int dtype, const D2Q9Args& a, const double* rho0,
 
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// regridding hand-off
+constexpr int kMaxBuffer = 8;      // LKS_MAX_BUFFER
+hipError_t launch_tag_buffer(const uint8_t* flags, uint8_t* out, int nx, int ny, int bc_x, int bc_y,
+                             int b, hipStream_t s);
+hipError_t launch_tag_tiles(const uint8_t* levels, int* counts, int nx, int ny, int level, int ts,
+                            hipStream_t s);
+
 // clears nwords 8-byte words with a fill kernel
 hipError_t launch_zero(void* p, long long nwords, hipStream_t s);
 

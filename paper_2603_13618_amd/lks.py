@@ -64,6 +64,11 @@ class Config(ctypes.Structure):
                 ("ext_reserved", ctypes.c_int32), ("thr_ext", (ctypes.c_double * 2) * MAX_EXT)]
 
 
+class Box(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int32), ("y0", ctypes.c_int32), ("x1", ctypes.c_int32),
+                ("y1", ctypes.c_int32)]
+
+
 class Buffers(ctypes.Structure):
     _fields_ = [("pop", ctypes.c_void_p * 2), ("sensors", ctypes.c_void_p),
                 ("flags", ctypes.c_void_p), ("sums", ctypes.c_void_p),
@@ -101,6 +106,10 @@ def lib():
             "lks_status_str": ([I32], ctypes.c_char_p),
             "lks_last_error": ([P], ctypes.c_char_p),
             "lks_copy_probe": ([P, P, ctypes.c_size_t, P], I32),
+            "lks_tag_buffer": ([P, I32, P, P], I32),
+            "lks_tag_tiles": ([P, P, I32, I32, P], I32),
+            "lks_cluster": ([P, I32, I32, I32, ctypes.c_double, I32, ctypes.POINTER(Box), I32,
+                             ctypes.POINTER(I32)], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -199,6 +208,21 @@ class Lattice:
                               _stream_handle(dev), ctypes.byref(self.ctx))
         _check(st, None)
 
+    def tag_buffer(self, b=2, flags=None, out=None):
+        """Buffer layer of b cells around the tagged cells of `flags` (default:
+        this context's flag map): uint8 levels [ny, nx] on the device."""
+        flags = self.flags if flags is None else flags
+        out = torch.empty((self.ny, self.nx), dtype=torch.uint8, device=self.device) if out is None else out
+        _check(lib().lks_tag_buffer(self.ctx, int(b), _ptr(flags), _ptr(out)), self.ctx)
+        return out
+
+    def tag_tiles(self, levels, level=1, ts=8, out=None):
+        """Cells at level >= `level` per ts x ts tile: int32 [ceil(ny/ts), ceil(nx/ts)]."""
+        shape = (-(-self.ny // ts), -(-self.nx // ts))
+        out = torch.empty(shape, dtype=torch.int32, device=self.device) if out is None else out
+        _check(lib().lks_tag_tiles(self.ctx, _ptr(levels), int(level), int(ts), _ptr(out)), self.ctx)
+        return out
+
     def ext(self, name):
         """The sensor plane of extension sensor `name` (must be in ext)."""
         k = EXT_NAMES.index(name)
@@ -285,6 +309,22 @@ class Lattice:
     def adjoint_init(self, rho0, ux0, uy0, lam0, gux, guy):
         _check(lib().lks_adjoint_init(self.ctx, _ptr(rho0), _ptr(ux0), _ptr(uy0), _ptr(lam0),
                                       _ptr(gux), _ptr(guy)), self.ctx)
+
+
+def cluster(counts, nx, ny, ts, eff=0.98, min_tiles=1, max_boxes=None):
+    """Berger-Rigoutsos patches of a host tile-count array (as written by
+    Lattice.tag_tiles): list of (x0, y0, x1, y1) cell boxes, half-open."""
+    c = np.ascontiguousarray(counts, dtype=np.int32)
+    if max_boxes is None:
+        max_boxes = max(int(np.count_nonzero(c)), 1)       # at most one box per tagged tile
+    boxes = (Box * max_boxes)()
+    n = ctypes.c_int32()
+    st = lib().lks_cluster(c.ctypes.data_as(ctypes.c_void_p), int(nx), int(ny), int(ts), float(eff),
+                           int(min_tiles), boxes, int(max_boxes), ctypes.byref(n))
+    if st != 0:
+        raise LksError(st, f"lks_cluster needs {n.value} boxes (room for {max_boxes})"
+                       if n.value > max_boxes else "invalid clustering arguments")
+    return [(b.x0, b.y0, b.x1, b.y1) for b in boxes[: n.value]]
 
 
 def copy_probe(dst, src):

@@ -46,6 +46,8 @@ def parse():
                    help="also time the BF16/FP16 storage forms on the 8192^2 workload")
     p.add_argument("--ext", action="store_true",
                    help="also time the fused steps with every extension sensor on")
+    p.add_argument("--regrid", action="store_true",
+                   help="also time the regridding hand-off on the final flag map")
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
     p.add_argument("--workload", choices=["smooth4096", "riemann2048", "smooth8192-bf16",
                                           "smooth8192-f16", "adjoint1024", "smooth4096-ext",
@@ -219,6 +221,8 @@ def main():
     traffic = traffic_entry(n * n)
     copy_gbps = copy_ceiling(torch, lks, dev, ev, 9 * n * n * 4)
 
+    regrid = time_regrid(torch, lks, lat, ev) if args.regrid else None
+
     # ---- the unfused baseline (three passes per step) on the same state
     lat.init(rho, ux, uy)
     lat.step(2, fused=False)
@@ -276,6 +280,8 @@ def main():
         out["forms"] = time_forms(torch, lks, inputs, workloads, dev, ev)
     if args.ext:
         out["ext"] = time_ext(torch, lks, inputs, workloads, dev, ev)
+    if regrid is not None:
+        out["regrid"] = regrid
 
     del lat
     torch.cuda.empty_cache()
@@ -284,6 +290,40 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def time_regrid(torch, lks, lat, ev, b=2, ts=8, eff=0.98):
+    """The regridding hand-off on the current flag map: buffer layer of b cells
+    and tile counts on the device (HIP events on the library's stream), then
+    the host clustering of the counts (wall clock), 2 buffer cells and 98 %
+    efficiency as in the paper."""
+    lv = lat.tag_buffer(b)
+    counts = lat.tag_tiles(lv, 1, ts)
+    torch.cuda.synchronize()
+    reps = 20
+    s, e = ev(), ev()
+    s.record()
+    for _ in range(reps):
+        lat.tag_buffer(b, out=lv)
+    e.record()
+    torch.cuda.synchronize()
+    t_buf = s.elapsed_time(e) / reps * 1e-3
+    s.record()
+    for _ in range(reps):
+        lat.tag_tiles(lv, 1, ts, out=counts)
+    e.record()
+    torch.cuda.synchronize()
+    t_tiles = s.elapsed_time(e) / reps * 1e-3
+    c = counts.cpu().numpy()
+    t0 = time.perf_counter()
+    boxes = lks.cluster(c, lat.nx, lat.ny, ts, eff)
+    t_cl = time.perf_counter() - t0
+    cells = lat.nx * lat.ny
+    area = sum((x1 - x0) * (y1 - y0) for x0, y0, x1, y1 in boxes)
+    return {"buffer_us": round(t_buf * 1e6, 2), "buffer_GBps": round(2 * cells / t_buf / 1e9, 1),
+            "tiles_us": round(t_tiles * 1e6, 2), "tiles_GBps": round(cells / t_tiles / 1e9, 1),
+            "cluster_ms": round(t_cl * 1e3, 2), "boxes": len(boxes),
+            "efficiency": round(float(c.sum()) / max(area, 1), 4), "b": b, "ts": ts, "eff": eff}
 
 
 def copy_ceiling(torch, lks, dev, ev, nbytes):

@@ -9,9 +9,15 @@
 // rows.  Ghost cells follow the lattice's boundary conditions (periodic:
 // wrap; outflow: repeat the edge cell).
 //
+// Levels are handled as 2-bit thermometer codes in the bytes of 32-bit words
+// (0, 1, 3 for levels 0, 1, 2), so the maximum is a bitwise OR over four
+// cells at once and the x window is a set of byte shifts of neighbouring
+// words.
+//
 // Tile counts: the number of cells at level >= L in each ts x ts tile (the
-// tiles at the high edges may be partial); one wave per tile, each lane sums
-// a strided share of the tile and the wave reduces with shuffles.
+// tiles at the high edges may be partial): on packed words with popcounts
+// and a segmented shuffle reduction where the row length and tile size
+// allow it, else one wave per tile.
 #include "lks_device.h"
 #include "lks_internal.h"
 
@@ -19,56 +25,111 @@ namespace lks {
 
 namespace {
 
-constexpr int kTX = 128;               // output cells per workgroup tile, x
+constexpr int kTX = 256;               // output cells per workgroup tile, x (64 words)
 constexpr int kTY = 16;                // and y
 constexpr int kMaxB = kMaxBuffer;
+constexpr int kWX = kTX / 4;           // output words per tile row
+constexpr int kPadW = 2;               // halo words on each side (b <= 8 cells)
+constexpr int kSW = kWX + 2 * kPadW;   // staged words per row
 
 __device__ __forceinline__ int wrap_or_clamp(int j, int n, int bc)
 {
     if (bc == 0) {
-        j %= n;
+        if (j >= -n && j < 2 * n) return j < 0 ? j + n : (j >= n ? j - n : j);   // one period off
+        j %= n;                                                                  // tiny grids
         return j < 0 ? j + n : j;
     }
     return j < 0 ? 0 : (j >= n ? n - 1 : j);
 }
 
+// Levels 0, 1, 2 as the thermometer codes 0, 1, 3 in each byte: the maximum
+// of levels is then the bitwise OR of codes, four cells per 32-bit word.
+__device__ __forceinline__ uint32_t to_code(uint32_t flags4)
+{
+    const uint32_t lv = flags4 & 0x03030303u;
+    return lv | ((lv >> 1) & 0x01010101u);
+}
+__device__ __forceinline__ uint32_t to_level(uint32_t code4)
+{
+    return (code4 & 0x01010101u) + ((code4 >> 1) & 0x01010101u);
+}
+// bytes [r, r + 4) of the 8-byte little-endian pair (lo, hi), r in 0..3
+__device__ __forceinline__ uint32_t bytes_at(uint32_t lo, uint32_t hi, int r)
+{
+    return r == 0 ? lo : __builtin_amdgcn_alignbyte(hi, lo, r);
+}
+
+// One workgroup: a kTX x kTY output tile.  Stage the tile's codes with a
+// b-row and kPadW-word halo in LDS, OR along x over 2b + 1 cells (byte
+// shifts of neighbouring words), then along y over 2b + 1 rows.
+template <int B>
 __global__ __launch_bounds__(kBlock) void buffer_kernel(const uint8_t* __restrict__ flags,
                                                         uint8_t* __restrict__ out, int nx, int ny,
-                                                        int bc_x, int bc_y, int b, int tiles_x)
+                                                        int bc_x, int bc_y, int tiles_x, int aligned4)
 {
-    __shared__ uint8_t src[kTY + 2 * kMaxB][kTX + 2 * kMaxB];
-    __shared__ uint8_t rowmax[kTY + 2 * kMaxB][kTX];
+    constexpr int b = B;
+    __shared__ uint32_t src[kTY + 2 * kMaxB][kSW];
+    __shared__ uint32_t rowor[kTY + 2 * kMaxB][kWX];
     const int X0 = (blockIdx.x % tiles_x) * kTX;
     const int Y0 = (blockIdx.x / tiles_x) * kTY;
-    const int W = kTX + 2 * b, H = kTY + 2 * b;
+    const int H = kTY + 2 * b;
+    // interior tiles of rows whose length is a multiple of 4 load whole words
+    const bool words = aligned4 && (nx % 4 == 0) && X0 >= 4 * kPadW && X0 + kTX + 4 * kPadW <= nx;
 
-    // stage the tile and its halo (levels only)
-    for (int e = threadIdx.x; e < W * H; e += kBlock) {
-        const int r = e / W, c = e % W;
+    for (int e = threadIdx.x; e < H * kSW; e += kBlock) {
+        const int r = e / kSW, w = e % kSW;
         const int gy = wrap_or_clamp(Y0 + r - b, ny, bc_y);
-        const int gx = wrap_or_clamp(X0 + c - b, nx, bc_x);
-        src[r][c] = flags[(long long)gy * nx + gx] & 3;
+        const uint8_t* row = flags + (long long)gy * nx;
+        uint32_t v;
+        if (words) {
+            v = *reinterpret_cast<const uint32_t*>(row + X0 + 4 * (w - kPadW));
+        } else {
+            v = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int gx = wrap_or_clamp(X0 + 4 * (w - kPadW) + k, nx, bc_x);
+                v |= (uint32_t)row[gx] << (8 * k);
+            }
+        }
+        src[r][w] = to_code(v);
     }
     __syncthreads();
-    // maximum along x over 2b + 1 columns
-    for (int e = threadIdx.x; e < kTX * H; e += kBlock) {
-        const int r = e / kTX, c = e % kTX;
-        uint8_t m = 0;
-        for (int k = 0; k <= 2 * b; ++k) m = max(m, src[r][c + k]);
-        rowmax[r][c] = m;
+    for (int e = threadIdx.x; e < H * kWX; e += kBlock) {
+        const int r = e / kWX, w = e % kWX;
+        const uint32_t a0 = src[r][w], a1 = src[r][w + 1], a2 = src[r][w + 2], a3 = src[r][w + 3],
+                       a4 = src[r][w + 4];
+        // cells 4w .. 4w+3 of the tile sit in word w + kPadW = a2; a cell
+        // shift s in [-b, b] reads bytes from 4 (w + kPadW) + s on
+        const uint32_t win[5] = {a0, a1, a2, a3, a4};
+        uint32_t m = 0;
+#pragma unroll
+        for (int sh = -b; sh <= b; ++sh) {
+            const int p = 4 * kPadW + sh;              // byte offset in the window, 0 .. 16
+            const int q = p >> 2, rr = p & 3;
+            const uint32_t lo = win[q], hi = q < 4 ? win[q + 1] : 0u;
+            m |= bytes_at(lo, hi, rr);
+        }
+        rowor[r][w] = m;
     }
     __syncthreads();
-    // then along y over 2b + 1 rows
-    for (int e = threadIdx.x; e < kTX * kTY; e += kBlock) {
-        const int r = e / kTX, c = e % kTX;
-        const int x = X0 + c, y = Y0 + r;
-        if (x >= nx || y >= ny) continue;
-        uint8_t m = 0;
-        for (int k = 0; k <= 2 * b; ++k) m = max(m, rowmax[r + k][c]);
-        out[(long long)y * nx + x] = m;
+    for (int e = threadIdx.x; e < kTY * kWX; e += kBlock) {
+        const int r = e / kWX, w = e % kWX;
+        const int y = Y0 + r, x = X0 + 4 * w;
+        if (y >= ny || x >= nx) continue;
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k <= 2 * b; ++k) m |= rowor[r + k][w];
+        const uint32_t lv = to_level(m);
+        uint8_t* dst = out + (long long)y * nx + x;
+        if (aligned4 && x + 4 <= nx && nx % 4 == 0) {
+            *reinterpret_cast<uint32_t*>(dst) = lv;
+        } else {
+            for (int k = 0; k < 4 && x + k < nx; ++k) dst[k] = (uint8_t)(lv >> (8 * k));
+        }
     }
 }
 
+// Tile counts, general form: one wave per tile, lanes stride over its cells.
 __global__ __launch_bounds__(kBlock) void tiles_kernel(const uint8_t* __restrict__ levels,
                                                        int* __restrict__ counts, int nx, int ny,
                                                        int level, int ts, int tiles_x, int ntiles)
@@ -88,6 +149,40 @@ __global__ __launch_bounds__(kBlock) void tiles_kernel(const uint8_t* __restrict
     if (lane == 0) counts[tile] = n;
 }
 
+// Tile counts on packed words (nx a multiple of 256, ts in 4, 8, .., 64): each
+// thread counts one 4-cell word per row of its tile column segment; the
+// ts/4 words x ts rows of a tile are spread over a group of lanes and reduced
+// with shuffles.  Thread t of the grid owns word column wc and tile row ty.
+__global__ __launch_bounds__(kBlock) void tiles_words_kernel(const uint8_t* __restrict__ levels,
+                                                             int* __restrict__ counts, int nx, int ny,
+                                                             int level, int ts, int tiles_x, int tiles_y)
+{
+    const int wpt = ts / 4;                         // words per tile row (1 .. 16)
+    const int words_x = nx / 4;
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const int wc = (int)(t % words_x);              // word column
+    const int ty = (int)(t / words_x);              // tile row
+    const bool live = ty < tiles_y;
+    int n = 0;
+    if (live) {
+        const int y0 = ty * ts, y1 = min(y0 + ts, ny);
+        const uint32_t* col = reinterpret_cast<const uint32_t*>(levels) + wc;
+        for (int y = y0; y < y1; ++y) {
+            const uint32_t lv = col[(long long)y * words_x] & 0x03030303u;
+            const uint32_t hit = level == 1 ? ((lv | (lv >> 1)) & 0x01010101u) : ((lv >> 1) & 0x01010101u);
+            n += __builtin_popcount(hit);
+        }
+    }
+    // lanes wc .. wc + wpt - 1 of one tile are adjacent (words_x is a
+    // multiple of wpt unless the last tile is partial, handled by the mask)
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int off = 1; off < wpt; off <<= 1) {
+        const int other = __shfl_down(n, off, kWave);
+        n += (lane % wpt) + off < wpt ? other : 0;
+    }
+    if (live && wc % wpt == 0) counts[(long long)ty * tiles_x + wc / wpt] = n;
+}
+
 } // namespace
 
 hipError_t launch_tag_buffer(const uint8_t* flags, uint8_t* out, int nx, int ny, int bc_x, int bc_y,
@@ -95,8 +190,16 @@ hipError_t launch_tag_buffer(const uint8_t* flags, uint8_t* out, int nx, int ny,
 {
     if (b < 0 || b > kMaxB) return hipErrorInvalidValue;
     const int tiles_x = (nx + kTX - 1) / kTX, tiles_y = (ny + kTY - 1) / kTY;
-    buffer_kernel<<<dim3((unsigned)(tiles_x * tiles_y)), dim3(kBlock), 0, s>>>(flags, out, nx, ny, bc_x,
-                                                                              bc_y, b, tiles_x);
+    const int aligned4 = ((uintptr_t)flags % 4 == 0) && ((uintptr_t)out % 4 == 0);
+    const dim3 grid((unsigned)(tiles_x * tiles_y)), block(kBlock);
+    switch (b) {
+#define LKS_BUFFER_CASE(B)                                                                          \
+    case B: buffer_kernel<B><<<grid, block, 0, s>>>(flags, out, nx, ny, bc_x, bc_y, tiles_x, aligned4); break;
+        LKS_BUFFER_CASE(0) LKS_BUFFER_CASE(1) LKS_BUFFER_CASE(2) LKS_BUFFER_CASE(3) LKS_BUFFER_CASE(4)
+        LKS_BUFFER_CASE(5) LKS_BUFFER_CASE(6) LKS_BUFFER_CASE(7) LKS_BUFFER_CASE(8)
+#undef LKS_BUFFER_CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -104,6 +207,16 @@ hipError_t launch_tag_tiles(const uint8_t* levels, int* counts, int nx, int ny, 
                             hipStream_t s)
 {
     const int tiles_x = (nx + ts - 1) / ts, tiles_y = (ny + ts - 1) / ts;
+    // packed path: whole words, tiles of 4 .. 64 cells aligned to the wave's
+    // lane groups (64 / (ts/4) tiles per wave)
+    const int wpt = ts / 4;
+    if ((uintptr_t)levels % 4 == 0 && nx % 4 == 0 && ts % 4 == 0 && (wpt & (wpt - 1)) == 0 &&
+        (nx / 4) % kWave == 0) {
+        const long long threads = (long long)(nx / 4) * tiles_y;
+        tiles_words_kernel<<<dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(
+            levels, counts, nx, ny, level, ts, tiles_x, tiles_y);
+        return hipGetLastError();
+    }
     const int ntiles = tiles_x * tiles_y;
     const int per_block = kBlock / kWave;
     tiles_kernel<<<dim3((unsigned)((ntiles + per_block - 1) / per_block)), dim3(kBlock), 0, s>>>(

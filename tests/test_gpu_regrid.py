@@ -21,8 +21,10 @@ def _random_flags(ny, nx, seed):
     return f
 
 
+# (1024 and 1280 wide: interior tiles take the packed word paths)
 @pytest.mark.parametrize("q,nx,ny,bc", [(9, 300, 70, (0, 0)), (9, 5, 3, (0, 0)), (25, 257, 130, (1, 1)),
-                                        (25, 129, 17, (0, 1)), (25, 64, 64, (1, 0))])
+                                        (25, 129, 17, (0, 1)), (25, 64, 64, (1, 0)),
+                                        (9, 1024, 40, (0, 0)), (25, 1280, 37, (1, 1))])
 @pytest.mark.parametrize("b", [0, 2, 5, 8])
 def test_buffer_and_tiles_match_oracle(q, nx, ny, bc, b):
     kw = dict(tau=0.6) if q == 9 else dict(mu=1e-3, dt=1e-4, dx=1e-2, bc=bc)

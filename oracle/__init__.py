@@ -16,5 +16,10 @@ from .oracle import (  # noqa: F401
     flags_from_sensors,
     ext_sensors,
     EXT_NAMES,
+    cv_of,
+    ddf_equilibrium,
+    ddf_moments,
+    ddf_step,
+    ddf_run,
     NSUMS,
 )

@@ -667,6 +667,295 @@ long orc_d2q25_step(int nx, int ny, double mu, double dt, double dx, int bc_x, i
 }
 
 /* ------------------------------------------------------------------------ */
+/* D2Q25 double distribution (f, g) with the quasi-equilibrium collision     */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper's kinetic model (Sec. II.A.1-2): f carries mass, momentum and the
+ * translational energy, g the non-translational internal energy (the
+ * internal non-translational split, eq. energy_eq_1_rykov):
+ *   rho = sum f, rho u = sum v f, E = sum (g + |v|^2/2 f) = rho C_v T + rho |u|^2/2,
+ *   g^eq = (C_v - R D/2) T f^eq, C_v = R/(gamma - 1), R = 1, D = 2.
+ * Collision (eq. new_collision_fi): Omega = -(f - f*)/tau1 - (f* - f^eq)/tau2.
+ * For Pr <= 1 the heat flux is the quasi-conserved field (Sec. II.A.2): the
+ * first stage relaxes the stresses with tau1, the second the heat flux with
+ * tau2, so mu = tau1 p and kappa = C_p p tau2, Pr = tau1/tau2.  READING (the
+ * paper takes the quasi-equilibria from a companion reference): f* = f^eq +
+ * w_i (q_f . v_i)(|v_i|^2/(D+2) - 1), the Grad heat-flux term built from the
+ * translational heat flux q_f = 1/2 sum |v-u|^2 (v-u) f (third-order Hermite
+ * term: zero mass, momentum, energy and stress on the GH5 quadrature); g* =
+ * g^eq + w_i (q_g . v_i), q_g = sum (v - u) g (first-order Hermite term).
+ * Then f*, g* keep every conserved field and carry the heat fluxes of f, g.
+ * Parity of this reading is unpinned against the paper; its transport
+ * (viscosity tau1 T, diffusivity tau2 T, so Pr = tau1/tau2) and gamma are
+ * pinned by the oracle tests.
+ * Layout: state [2*25][n], f planes 0..24 then g planes 25..49.
+ */
+typedef struct {
+    double rho, ux, uy, E, T, qfx, qfy, qgx, qgy;
+} orc_ddf_mom;
+
+static orc_ddf_mom ddf_moments(const orc_rule* r, const double* f, const double* g, double cv)
+{
+    orc_ddf_mom m = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double jx = 0.0, jy = 0.0;
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            const int i = 5 * a + b;
+            m.rho += f[i];
+            jx += r->v[a] * f[i];
+            jy += r->v[b] * f[i];
+            m.E += g[i] + 0.5 * (r->v[a] * r->v[a] + r->v[b] * r->v[b]) * f[i];
+        }
+    m.ux = jx / m.rho;
+    m.uy = jy / m.rho;
+    m.T = (m.E / m.rho - 0.5 * (m.ux * m.ux + m.uy * m.uy)) / cv;
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            const int i = 5 * a + b;
+            const double cx = r->v[a] - m.ux, cy = r->v[b] - m.uy;
+            const double c2 = cx * cx + cy * cy;
+            m.qfx += 0.5 * c2 * cx * f[i];
+            m.qfy += 0.5 * c2 * cy * f[i];
+            m.qgx += cx * g[i];
+            m.qgy += cy * g[i];
+        }
+    return m;
+}
+
+/* equilibria and quasi-equilibria of one cell */
+static void ddf_eq_qe(const orc_rule* r, const orc_ddf_mom* m, double cv, double* feq, double* geq,
+                      double* fst, double* gst)
+{
+    const int D = 2;
+    grad_hermite_feq(r, m->rho, m->ux, m->uy, m->T, feq);
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            const int i = 5 * a + b;
+            const double w = r->w[a] * r->w[b], vx = r->v[a], vy = r->v[b];
+            const double v2 = vx * vx + vy * vy;
+            geq[i] = (cv - 0.5 * D) * m->T * feq[i];
+            fst[i] = feq[i] + w * (m->qfx * vx + m->qfy * vy) * (v2 / (D + 2) - 1.0);
+            gst[i] = geq[i] + w * (m->qgx * vx + m->qgy * vy);
+        }
+}
+
+/* sensors of one cell: s[0] = |sum f ln(f/f^eq)| + |sum g ln(g/g^eq)|,
+ * s[1] = sum |f^neq| + sum |g^neq|, s[2] = S_PI (f), s[3] = |sum v g^neq +
+ * sum v |v|^2/2 f^neq|, s[4] = sum |f* - f^eq| + sum |g* - g^eq|
+ * (eqs. HKL-sensor, sensor-neq-kin, sensor-TauNS-kin, sensor-qNSF-kin-ryk,
+ * Sensor-qe-kin).  Returns 1 on a positivity fault (s[0] = +inf). */
+static int ddf_sensors(const orc_rule* r, const double* f, const double* g, const double* feq,
+                       const double* geq, const double* fst, const double* gst, double* s)
+{
+    int fault = 0;
+    double klf = 0.0, klg = 0.0, neq = 0.0, pxx = 0.0, pxy = 0.0, pyy = 0.0, qx = 0.0, qy = 0.0,
+           qe = 0.0;
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            const int i = 5 * a + b;
+            const double vx = r->v[a], vy = r->v[b];
+            const double fn = f[i] - feq[i], gn = g[i] - geq[i];
+            if (!(f[i] > 0.0) || !(feq[i] > 0.0) || !(g[i] > 0.0) || !(geq[i] > 0.0)) {
+                fault = 1;
+            } else {
+                klf += f[i] * log(f[i] / feq[i]);
+                klg += g[i] * log(g[i] / geq[i]);
+            }
+            neq += fabs(fn) + fabs(gn);
+            pxx += vx * vx * fn;
+            pxy += vx * vy * fn;
+            pyy += vy * vy * fn;
+            const double e = 0.5 * (vx * vx + vy * vy);
+            qx += vx * (gn + e * fn);
+            qy += vy * (gn + e * fn);
+            qe += fabs(fst[i] - feq[i]) + fabs(gst[i] - geq[i]);
+        }
+    s[0] = fault ? INFINITY : fabs(klf) + fabs(klg);
+    s[1] = neq;
+    s[2] = sqrt(pxx * pxx + 2.0 * pxy * pxy + pyy * pyy);
+    s[3] = sqrt(qx * qx + qy * qy);
+    s[4] = qe;
+    return fault;
+}
+
+static uint8_t ddf_flag(const double* s, const double* thr, unsigned mask, int fault)
+{
+    int level = 0;
+    for (int k = 0; k < 5; ++k) {
+        if (!(mask & (1u << k))) continue;
+        const int l = (s[k] > thr[2 * k]) + (s[k] > thr[2 * k + 1]);
+        if (l > level) level = l;
+    }
+    if (fault) return (uint8_t)(2 | 0x80);
+    return (uint8_t)level;
+}
+
+/* equilibrium (f^eq, g^eq) of n cells from FP64 fields: out [50][n] */
+int orc_ddf_equilibrium(long n, const double* rho, const double* ux, const double* uy,
+                        const double* T, double cv, double* out)
+{
+    orc_rule r;
+    rule_d2q25(&r);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) {
+        double fe[25];
+        grad_hermite_feq(&r, rho[c], ux[c], uy[c], T[c], fe);
+        for (int i = 0; i < 25; ++i) {
+            out[(long)i * n + c] = fe[i];
+            out[(long)(25 + i) * n + c] = (cv - 1.0) * T[c] * fe[i];
+        }
+    }
+    return 0;
+}
+
+/* per cell: out[0..3][n] = rho, ux, uy, T; then [4..99 +] the populations
+ * feq, geq, f*, g* ([100][n] starting at plane 4) when qe != NULL */
+int orc_ddf_moments(long n, const double* f, double cv, double* out, double* qe)
+{
+    orc_rule r;
+    rule_d2q25(&r);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) {
+        double fc[25], gc[25], fe[25], ge[25], fs[25], gs[25];
+        for (int i = 0; i < 25; ++i) {
+            fc[i] = f[(long)i * n + c];
+            gc[i] = f[(long)(25 + i) * n + c];
+        }
+        const orc_ddf_mom m = ddf_moments(&r, fc, gc, cv);
+        out[c] = m.rho;
+        out[n + c] = m.ux;
+        out[2 * n + c] = m.uy;
+        out[3 * n + c] = m.T;
+        if (qe) {
+            ddf_eq_qe(&r, &m, cv, fe, ge, fs, gs);
+            for (int i = 0; i < 25; ++i) {
+                qe[(long)i * n + c] = fe[i];
+                qe[(long)(25 + i) * n + c] = ge[i];
+                qe[(long)(50 + i) * n + c] = fs[i];
+                qe[(long)(75 + i) * n + c] = gs[i];
+            }
+        }
+    }
+    return 0;
+}
+
+/* One explicit-Euler FV step of (f, g): both distributions take the same
+ * dimension-by-dimension van Leer fluxes as the single-distribution step and
+ * the quasi-equilibrium collision; tau1 = mu/(rho T), tau2 = tau1/Pr.
+ * Sensors [5][n], flags and sums of the state the collision reads.  thr:
+ * [5][2]; sums[8]: mass, x/y momentum, total energy, totals of s[0..3]. */
+long orc_ddf_step(int nx, int ny, double mu, double prandtl, double cv, double dt, double dx,
+                  int bc_x, int bc_y, const double* f, double* fout, double* mom, double* sens,
+                  uint8_t* flags, const double* thr, unsigned mask, double* sums)
+{
+    orc_rule r;
+    rule_d2q25(&r);
+    const long n = (long)nx * ny;
+    double* rowsum = (double*)calloc((size_t)ny * ORC_NSUMS, sizeof(double));
+    long faults = 0;
+
+#pragma omp parallel for schedule(static) reduction(+ : faults)
+    for (int y = 0; y < ny; ++y) {
+        double* rs = rowsum + (size_t)y * ORC_NSUMS;
+        for (int x = 0; x < nx; ++x) {
+            const long c = (long)y * nx + x;
+            double fc[25], gc[25], fe[25], ge[25], fs[25], gs[25], s[5];
+            for (int i = 0; i < 25; ++i) {
+                fc[i] = f[(long)i * n + c];
+                gc[i] = f[(long)(25 + i) * n + c];
+            }
+            const orc_ddf_mom m = ddf_moments(&r, fc, gc, cv);
+            ddf_eq_qe(&r, &m, cv, fe, ge, fs, gs);
+            const int fault = ddf_sensors(&r, fc, gc, fe, ge, fs, gs, s);
+            faults += fault;
+            const double tau1 = mu / (m.rho * m.T), tau2 = tau1 / prandtl;
+            for (int dist = 0; dist < 2; ++dist)
+                for (int a = 0; a < 5; ++a)
+                    for (int b = 0; b < 5; ++b) {
+                        const int i = 5 * a + b;
+                        const double* fi = f + (long)(25 * dist + i) * n;
+                        const double vx = r.v[a], vy = r.v[b];
+                        double div = 0.0;
+                        if (vx != 0.0) {
+                            double q[5];
+                            for (int k = -2; k <= 2; ++k)
+                                q[k + 2] = fi[(long)y * nx + ghost(x + k, nx, bc_x)];
+                            div += (face_flux(vx, q[1], q[2], q[3], q[4]) -
+                                    face_flux(vx, q[0], q[1], q[2], q[3])) / dx;
+                        }
+                        if (vy != 0.0) {
+                            double q[5];
+                            for (int k = -2; k <= 2; ++k)
+                                q[k + 2] = fi[ghost(y + k, ny, bc_y) * nx + x];
+                            div += (face_flux(vy, q[1], q[2], q[3], q[4]) -
+                                    face_flux(vy, q[0], q[1], q[2], q[3])) / dx;
+                        }
+                        const double cur = dist ? gc[i] : fc[i];
+                        const double st = dist ? gs[i] : fs[i];
+                        const double eq = dist ? ge[i] : fe[i];
+                        const double omega = -(cur - st) / tau1 - (st - eq) / tau2;
+                        fout[(long)(25 * dist + i) * n + c] = cur - dt * div + dt * omega;
+                    }
+            if (mom) {
+                mom[c] = m.rho;
+                mom[n + c] = m.ux;
+                mom[2 * n + c] = m.uy;
+                mom[3 * n + c] = m.T;
+            }
+            if (sens)
+                for (int k = 0; k < 5; ++k) sens[(long)k * n + c] = s[k];
+            if (flags) flags[c] = ddf_flag(s, thr, mask, fault);
+            rs[0] += m.rho;
+            rs[1] += m.rho * m.ux;
+            rs[2] += m.rho * m.uy;
+            rs[3] += m.E;
+            for (int k = 0; k < 4; ++k) rs[4 + k] += s[k];
+        }
+    }
+    for (int k = 0; k < ORC_NSUMS; ++k) sums[k] = 0.0;
+    for (int y = 0; y < ny; ++y)
+        for (int k = 0; k < ORC_NSUMS; ++k) sums[k] += rowsum[(size_t)y * ORC_NSUMS + k];
+    free(rowsum);
+    return faults;
+}
+
+/* Run nsteps of the double distribution from f ([50][n], overwritten).
+ * Per step sums[step][8]; the last step's moments [4][n], sensors [5][n]
+ * and flags [n] when non-NULL.  thr [5][2]. */
+long orc_ddf_run(int nx, int ny, double mu, double prandtl, double cv, double dt, double dx,
+                 int bc_x, int bc_y, int nsteps, double* f, double* mom, double* sens,
+                 uint8_t* flags, const double* thr, unsigned mask, double* sums, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    const long n = (long)nx * ny;
+    double* a = f;
+    double* b = (double*)malloc(sizeof(double) * 50 * (size_t)n);
+    uint8_t* fl = (uint8_t*)malloc((size_t)n);
+    long faults = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        const int last = (s == nsteps - 1);
+        faults += orc_ddf_step(nx, ny, mu, prandtl, cv, dt, dx, bc_x, bc_y, a, b, last ? mom : NULL,
+                               last ? sens : NULL, fl, thr, mask, sums + 8 * (long)s);
+        if (last && flags) memcpy(flags, fl, (size_t)n);
+        double* t = a;
+        a = b;
+        b = t;
+    }
+    if (a != f) {
+        memcpy(f, a, sizeof(double) * 50 * (size_t)n);
+        free(a);
+    } else {
+        free(b);
+    }
+    free(fl);
+    return faults;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Multi-step drivers                                                        */
 /* ------------------------------------------------------------------------ */
 

@@ -57,6 +57,16 @@ def _load():
                                 ctypes.c_int]
         lib.orc_run.restype = ctypes.c_long
         lib.orc_ext_sensors.argtypes = [ctypes.c_int, ctypes.c_long, P, ctypes.c_double, P]
+        D = ctypes.c_double
+        lib.orc_ddf_equilibrium.argtypes = [ctypes.c_long, P, P, P, P, D, P]
+        lib.orc_ddf_moments.argtypes = [ctypes.c_long, P, D, P, P]
+        lib.orc_ddf_step.argtypes = [ctypes.c_int, ctypes.c_int, D, D, D, D, D, ctypes.c_int,
+                                     ctypes.c_int, P, P, P, P, P, P, ctypes.c_uint, P]
+        lib.orc_ddf_step.restype = ctypes.c_long
+        lib.orc_ddf_run.argtypes = [ctypes.c_int, ctypes.c_int, D, D, D, D, D, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_uint, P,
+                                    ctypes.c_int]
+        lib.orc_ddf_run.restype = ctypes.c_long
         lib.orc_num_ext.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -121,6 +131,67 @@ def ext_sensors(q, f, par):
     if lib.orc_ext_sensors(q, f[0].size, _p(f), float(par), _p(out)) != 0:
         raise ValueError(q)
     return out
+
+
+# ---- D2Q25 double distribution (f, g) with the quasi-equilibrium collision
+def cv_of(gamma):
+    """Specific heat at constant volume C_v = R/(gamma - 1), R = 1."""
+    return 1.0 / (gamma - 1.0)
+
+
+def ddf_equilibrium(rho, ux, uy, T, gamma=1.4):
+    """(f^eq, g^eq) [50, *shape] of the fields (f planes, then g planes)."""
+    rho = _f64(rho)
+    n = rho.size
+    out = np.empty((50,) + rho.shape)
+    _load().orc_ddf_equilibrium(n, _p(rho), _p(_f64(ux)), _p(_f64(uy)), _p(_f64(T)),
+                                cv_of(gamma), _p(out))
+    return out
+
+
+def ddf_moments(f, gamma=1.4, qe=False):
+    """rho, ux, uy, T [4, *shape] of a double-distribution state [50, *shape];
+    with qe=True also (f^eq, g^eq, f*, g*) [100, *shape]."""
+    f = _f64(f)
+    n = f[0].size
+    out = np.empty((4,) + f.shape[1:])
+    q = np.empty((100,) + f.shape[1:]) if qe else None
+    _load().orc_ddf_moments(n, _p(f), cv_of(gamma), _p(out), _p(q))
+    return (out, q) if qe else out
+
+
+def _thr5(thr):
+    t = np.full(10, np.inf)
+    if thr is not None:
+        t[:] = np.asarray(thr, dtype=np.float64).reshape(10)
+    return t
+
+
+def ddf_step(f, mu, dt, dx, bc=(1, 1), gamma=1.4, prandtl=0.71, thr=None, mask=0):
+    """One step of the double distribution.  Returns dict(f, mom, sens [5],
+    flags, sums, faults)."""
+    f = _f64(f)
+    _, ny, nx = f.shape
+    fo = np.empty_like(f)
+    mom, sens = np.empty((4, ny, nx)), np.empty((5, ny, nx))
+    flags = np.empty((ny, nx), np.uint8)
+    sums = np.empty(NSUMS)
+    nf = _load().orc_ddf_step(nx, ny, mu, prandtl, cv_of(gamma), dt, dx, bc[0], bc[1], _p(f), _p(fo),
+                              _p(mom), _p(sens), _p(flags), _p(_thr5(thr)), mask, _p(sums))
+    return dict(f=fo, mom=mom, sens=sens, flags=flags, sums=sums, faults=int(nf))
+
+
+def ddf_run(f0, nsteps, mu, dt, dx, bc=(1, 1), gamma=1.4, prandtl=0.71, thr=None, mask=0,
+            nthreads=0):
+    """Run nsteps of the double distribution from f0 [50, ny, nx]."""
+    f = _f64(f0).copy()
+    _, ny, nx = f.shape
+    mom, sens = np.empty((4, ny, nx)), np.empty((5, ny, nx))
+    flags = np.empty((ny, nx), np.uint8)
+    sums = np.zeros((max(nsteps, 1), NSUMS))
+    nf = _load().orc_ddf_run(nx, ny, mu, prandtl, cv_of(gamma), dt, dx, bc[0], bc[1], nsteps, _p(f),
+                             _p(mom), _p(sens), _p(flags), _p(_thr5(thr)), mask, _p(sums), nthreads)
+    return dict(f=f, mom=mom, sens=sens, flags=flags, sums=sums[:nsteps], faults=int(nf))
 
 
 def _thr(thr):

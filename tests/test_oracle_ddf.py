@@ -1,0 +1,198 @@
+"""Pins of the oracle's D2Q25 double-distribution model (f, g, quasi-
+equilibrium collision): equilibrium round trip and fixed point, exact
+conservation of mass, momentum and total energy, the moments the
+quasi-equilibria are built to keep, and the transport the model is meant to
+have -- shear viscosity mu, thermal diffusivity mu/(rho Pr) (so the Prandtl
+number is Pr = tau1/tau2 = 0.71) and the adiabatic exponent gamma = 1.4,
+measured from decaying shear and temperature waves and a standing sound wave
+(Sec. II.A.2, the NSF limit; Sec. IV, air)."""
+import numpy as np
+import pytest
+
+from paper_2603_13618_amd import inputs
+
+GAMMA, PR = 1.4, 0.71
+
+
+def _lattice(orc):
+    vx, vy, w = orc.lattice(25)
+    return vx[:, None, None], vy[:, None, None], w[:, None, None]
+
+
+def _noneq_state(orc, shape, seed, scale=2e-3):
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.1 * rng.standard_normal(shape)
+    ux, uy = 0.05 * rng.standard_normal(shape), 0.05 * rng.standard_normal(shape)
+    T = 1.0 + 0.1 * rng.standard_normal(shape)
+    f = orc.ddf_equilibrium(rho, ux, uy, T, GAMMA)
+    return f * (1.0 + scale * rng.standard_normal(f.shape))
+
+
+def test_equilibrium_round_trip_and_zero_sensors(orc):
+    rho, ux, uy = inputs.random_state((5, 7), seed=1, umax=0.1)
+    T = 1.0 + 0.3 * (rho - 1.0)
+    f = orc.ddf_equilibrium(rho, ux, uy, T, GAMMA)
+    m = orc.ddf_moments(f, GAMMA)
+    assert np.abs(m[0] - rho).max() < 1e-14 and np.abs(m[1] - ux).max() < 1e-14
+    assert np.abs(m[3] - T).max() < 1e-14
+    o = orc.ddf_step(f, 1e-3, 1e-4, 0.1, bc=(1, 1), gamma=GAMMA, prandtl=PR)
+    assert np.abs(o["sens"]).max() < 1e-13
+    # g^eq = (C_v - D/2) T f^eq with C_v = 1/(gamma - 1) = 2.5
+    assert np.allclose(f[25:], 1.5 * T * f[:25], rtol=1e-14)
+
+
+def test_uniform_state_is_a_fixed_point(orc):
+    u = np.ones((6, 6))
+    f = orc.ddf_equilibrium(0.9 * u, 0.05 * u, -0.02 * u, 1.1 * u, GAMMA)
+    o = orc.ddf_run(f, 5, 1e-3, 1e-3, 0.1, bc=(0, 0), gamma=GAMMA, prandtl=PR)
+    assert np.abs(o["f"] - f).max() < 1e-15
+
+
+def test_conservation_periodic(orc):
+    f = _noneq_state(orc, (24, 20), seed=3)
+    o = orc.ddf_run(f, 30, 2e-3, 2e-3, 1.0 / 24, bc=(0, 0), gamma=GAMMA, prandtl=PR)
+    s = o["sums"]
+    vx, vy, _ = _lattice(orc)
+    m0 = f[:25].sum()
+    jx0, jy0 = (vx * f[:25]).sum(), (vy * f[:25]).sum()
+    E0 = f[25:].sum() + (0.5 * (vx ** 2 + vy ** 2) * f[:25]).sum()
+    assert np.abs(s[:, 0] - m0).max() < 1e-13 * m0
+    assert np.abs(s[:, 1] - jx0).max() < 1e-13 * m0 and np.abs(s[:, 2] - jy0).max() < 1e-13 * m0
+    assert np.abs(s[:, 3] - E0).max() < 1e-13 * E0
+
+
+def test_quasi_equilibria_keep_the_designed_moments(orc):
+    f = _noneq_state(orc, (3, 4), seed=7, scale=5e-2)
+    m, q = orc.ddf_moments(f, GAMMA, qe=True)
+    feq, geq, fs, gs = q[:25], q[25:50], q[50:75], q[75:]
+    vx, vy, _ = _lattice(orc)
+    rho, ux, uy = m[0], m[1], m[2]
+    tol = 1e-13
+    for a, b in ((fs, feq),):
+        assert np.abs(a.sum(0) - rho).max() < tol
+        assert np.abs((vx * a).sum(0) - rho * ux).max() < tol
+        for p in (vx * vx, vx * vy, vy * vy):               # equilibrium stresses
+            assert np.abs((p * a).sum(0) - (p * b).sum(0)).max() < tol
+    cx, cy = vx - ux, vy - uy
+    heat = lambda h: (0.5 * (cx ** 2 + cy ** 2) * cx * h).sum(0)
+    assert np.abs(heat(fs) - heat(f[:25])).max() < tol     # f's heat flux is kept
+    assert np.abs(gs.sum(0) - geq.sum(0)).max() < tol
+    assert np.abs((cx * gs).sum(0) - (cx * f[25:]).sum(0)).max() < tol
+    E = f[25:].sum(0) + (0.5 * (vx ** 2 + vy ** 2) * f[:25]).sum(0)
+    Es = gs.sum(0) + (0.5 * (vx ** 2 + vy ** 2) * fs).sum(0)
+    assert np.abs(Es - E).max() < tol
+
+
+def _shear_run(orc, n, mu, steps_factor=0.2):
+    """A 2 x n periodic column with a shear wave u_x = U sin(2 pi y); returns
+    the decay rate of its mode and the expected rate nu k^2."""
+    y = (np.arange(n) + 0.5) / n
+    s = np.sin(2 * np.pi * y)[:, None] * np.ones((1, 2))
+    one = np.ones((n, 2))
+    rho0, T0 = 1.2, 1.5
+    f = orc.ddf_equilibrium(rho0 * one, 1e-3 * s, 0 * one, T0 * one, GAMMA)
+    expect = mu / rho0                           # nu
+    field = 1
+    dx = 1.0 / n
+    dt = 0.05 * dx / 2.857
+    k = 2 * np.pi
+    steps = int(steps_factor / (expect * k * k) / dt)
+    o1 = orc.ddf_run(f, 20, mu, dt, dx, bc=(0, 0), gamma=GAMMA, prandtl=PR)
+    o2 = orc.ddf_run(o1["f"], steps, mu, dt, dx, bc=(0, 0), gamma=GAMMA, prandtl=PR)
+    a1 = ((o1["mom"][field] - o1["mom"][field].mean()) * s).sum()
+    a2 = ((o2["mom"][field] - o2["mom"][field].mean()) * s).sum()
+    return -np.log(a2 / a1) / (steps * dt), expect * k * k
+
+
+def test_shear_viscosity(orc):
+    rate, expect = _shear_run(orc, 128, 0.01)
+    assert abs(rate / expect - 1) < 0.01
+
+
+def test_thermal_diffusivity_gives_the_prandtl_number(orc):
+    # heat relaxes with tau2 = tau1 / Pr: alpha = kappa / (rho C_p) = mu / (rho
+    # Pr); with the shear test this measures Pr = nu / alpha.  The isobaric
+    # start also excites a weak sound wave (alpha k / c_s ~ 0.05), so the rate
+    # is a least-squares fit of the log amplitude over one e-fold, which
+    # averages the acoustic ripple out.
+    n, mu = 128, 0.01
+    y = (np.arange(n) + 0.5) / n
+    s = np.sin(2 * np.pi * y)[:, None] * np.ones((1, 2))
+    one = np.ones((n, 2))
+    rho0, T0 = 1.2, 1.5
+    T = T0 * (1 + 1e-3 * s)
+    f = orc.ddf_equilibrium(rho0 * T0 / T, 0 * one, 0 * one, T, GAMMA)
+    dx = 1.0 / n
+    dt = 0.05 * dx / 2.857
+    k = 2 * np.pi
+    expect = mu / (rho0 * PR) * k * k
+    chunks = 40
+    chunk = int(1.0 / expect / dt / chunks)
+    t, amps = [], []
+    for i in range(chunks):
+        o = orc.ddf_run(f, chunk, mu, dt, dx, bc=(0, 0), gamma=GAMMA, prandtl=PR)
+        f = o["f"]
+        t.append((i + 1) * chunk * dt)
+        amps.append(((o["mom"][3] - o["mom"][3].mean()) * s).sum())
+    rate = -np.polyfit(t[5:], np.log(amps[5:]), 1)[0]
+    assert abs(rate / expect - 1) < 0.015
+
+
+def test_sound_speed_gives_gamma(orc):
+    # standing isentropic wave rho' = eps cos(k y): the density mode oscillates
+    # at omega = c_s k, c_s^2 = gamma T0 (R = 1); two successive zero crossings
+    # of the mode are half a period apart
+    n = 128
+    y = (np.arange(n) + 0.5) / n
+    c = np.cos(2 * np.pi * y)[:, None] * np.ones((1, 2))
+    one = np.ones((n, 2))
+    rho0, T0, eps = 1.0, 1.0, 1e-4
+    rho = rho0 * (1 + eps * c)
+    T = T0 * (1 + (GAMMA - 1) * eps * c)
+    f = orc.ddf_equilibrium(rho, 0 * one, 0 * one, T, GAMMA)
+    dx = 1.0 / n
+    dt = 0.05 * dx / 2.857
+    mu = 1e-4
+    k = 2 * np.pi
+    period = 2 * np.pi / (np.sqrt(GAMMA * T0) * k)
+    chunk = 10
+    t, amps = [], []
+    for it in range(int(1.3 * period / (chunk * dt))):
+        o = orc.ddf_run(f, chunk, mu, dt, dx, bc=(0, 0), gamma=GAMMA, prandtl=PR)
+        f = o["f"]
+        t.append((it + 1) * chunk * dt)
+        amps.append(((o["mom"][0] - rho0) * c).sum())
+    t, amps = np.array(t), np.array(amps)
+    cross = [t[i] - amps[i] * (t[i + 1] - t[i]) / (amps[i + 1] - amps[i])
+             for i in range(len(amps) - 1) if amps[i] * amps[i + 1] < 0]
+    assert len(cross) >= 2
+    omega = np.pi / (cross[1] - cross[0])
+    gamma = (omega / k) ** 2 / T0
+    assert abs(gamma / GAMMA - 1) < 0.01, gamma
+
+
+def test_sensors_of_a_quasi_equilibrium_state(orc):
+    # A state sitting at its own quasi-equilibrium (f = f*, g = g*) keeps the
+    # moments of the state it came from, so its quasi-equilibrium is itself:
+    # the QE sensor (eq. Sensor-qe-kin) then equals the non-equilibrium sensor
+    # (eq. sensor-neq-kin), and at rest the energy-flux sensor (eq.
+    # sensor-qNSF-kin-ryk) is the length of the carried heat flux q_f + q_g.
+    rng = np.random.default_rng(11)
+    shape = (3, 4)
+    rho = 1.0 + 0.1 * rng.standard_normal(shape)
+    T = 1.0 + 0.1 * rng.standard_normal(shape)
+    zero = np.zeros(shape)
+    x = orc.ddf_equilibrium(rho, zero, zero, T, GAMMA) * (1 + 3e-2 * rng.standard_normal((50,) + shape))
+    # remove the momentum the noise added, so that the state is at rest
+    vx, vy, w = _lattice(orc)
+    m = orc.ddf_moments(x, GAMMA)
+    x[:25] -= w * (vx * m[0] * m[1] + vy * m[0] * m[2])
+    m, q = orc.ddf_moments(x, GAMMA, qe=True)
+    assert np.abs(m[1]).max() < 1e-15 and np.abs(m[2]).max() < 1e-15
+    y = np.concatenate([q[50:75], q[75:]])
+    s = orc.ddf_step(y, 1e-3, 1e-5, 0.1, bc=(1, 1), gamma=GAMMA, prandtl=PR)["sens"]
+    assert np.allclose(s[4], s[1], rtol=1e-13, atol=0)
+    qf = [(0.5 * (vx ** 2 + vy ** 2) * c * x[:25]).sum(0) for c in (vx, vy)]
+    qg = [(c * x[25:]).sum(0) for c in (vx, vy)]
+    assert np.allclose(s[3], np.hypot(qf[0] + qg[0], qf[1] + qg[1]), rtol=1e-12, atol=0)
+    assert (s[0] > 0).all()

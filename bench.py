@@ -33,6 +33,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2603_13618_amd", "csrc", "d2q9.hip")
 # the fused FP32 step at the default launch shape (4 cells per thread)
 FUSED_KERNEL = "d2q9_fused_lds<float,4,false>"
 FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
+# the double-distribution step (FP32): 50 x 4 read + 50 x 4 written + 5 x 4
+# sensors + 1 flag per cell
+BYTES_F32_DDF = 421
+DDF_KERNEL = "d2q25_ddf_kernel<float,32,4>"
 
 
 def parse():
@@ -46,12 +50,14 @@ def parse():
                    help="also time the BF16/FP16 storage forms on the 8192^2 workload")
     p.add_argument("--ext", action="store_true",
                    help="also time the fused steps with every extension sensor on")
+    p.add_argument("--ddf", action="store_true",
+                   help="also time the D2Q25 double-distribution step on the 2048^2 Riemann problem")
     p.add_argument("--regrid", action="store_true",
                    help="also time the regridding hand-off on the final flag map")
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
     p.add_argument("--workload", choices=["smooth4096", "riemann2048", "smooth8192-bf16",
                                           "smooth8192-f16", "adjoint1024", "smooth4096-ext",
-                                          "riemann2048-ext"],
+                                          "riemann2048-ext", "riemann2048-ddf"],
                    default="smooth4096", help="workload of --mode kernel (profiling runs)")
     p.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                    help="assemble the traffic summary from four rocprofv3 --pmc output "
@@ -280,6 +286,8 @@ def main():
         out["forms"] = time_forms(torch, lks, inputs, workloads, dev, ev)
     if args.ext:
         out["ext"] = time_ext(torch, lks, inputs, workloads, dev, ev)
+    if args.ddf:
+        out["ddf"] = time_ddf(torch, lks, inputs, workloads, dev, ev)
     if regrid is not None:
         out["regrid"] = regrid
 
@@ -395,11 +403,59 @@ def time_ext(torch, lks, inputs, workloads, dev, ev):
     return res
 
 
+def ddf_lattice(lks, inputs, workloads, dev, steps):
+    """The double-distribution workload, initialised (FP32 storage)."""
+    wl = workloads.RIEMANN_2048_DDF
+    n = wl["nx"]
+    rho, ux, uy, T, states = inputs.riemann_quadrants(n, seed=wl["seed"])
+    dx = 1.0 / n
+    lat = lks.Lattice(25, n, n, "f32", mu=wl["mu"], dt=inputs.riemann_dt(states, dx, gamma=wl["gamma"]),
+                      dx=dx, bc=(1, 1), thr=wl["thr"], flag_mask=wl["flag_mask"],
+                      max_steps=max(steps, 1), model="ddf", gamma=wl["gamma"],
+                      prandtl=wl["prandtl"], thr_qe=wl["thr_qe"], device=dev)
+    lat.init(rho, ux, uy, T)
+    return lat
+
+
+def time_ddf(torch, lks, inputs, workloads, dev, ev):
+    """Fused double-distribution steps (timing only): whole steps, then the
+    step kernel alone between the two state buffers."""
+    k = 40
+    lat = ddf_lattice(lks, inputs, workloads, dev, k)
+    lat.step(3)
+    torch.cuda.synchronize()
+    s, e = ev(), ev()
+    s.record()
+    lat.step(k)
+    e.record()
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / k * 1e-3
+    src, dst = lat.pop[lat.current()[0]], lat.pop[1 - lat.current()[0]]
+    s.record()
+    for r in range(k):
+        lat.step_from(src, dst) if r % 2 == 0 else lat.step_from(dst, src)
+    e.record()
+    torch.cuda.synchronize()
+    tk = s.elapsed_time(e) / k * 1e-3
+    cells = lat.nx * lat.ny
+    res = {"workload": workloads.RIEMANN_2048_DDF["name"], "MLUPS": round(cells / t / 1e6, 1),
+           "us_per_step": round(t * 1e6, 1), "kernel": DDF_KERNEL, "kernel_us": round(tk * 1e6, 1),
+           "bytes_per_lup": BYTES_F32_DDF,
+           "GBps_model": round(BYTES_F32_DDF * cells / tk / 1e9, 1),
+           "frac_hbm": round(BYTES_F32_DDF * cells / tk / 1e9 / HBM_PEAK_GBPS, 4),
+           "faults": lat.check()}
+    del lat
+    torch.cuda.empty_cache()
+    return res
+
+
 def kernel_only(args, torch, lks, inputs, workloads, dev):
     """A short run of one of the other workloads (for profilers)."""
     if args.workload.endswith("-ext"):
         a, b = ext_lattices(lks, inputs, workloads, dev, args.steps)
         (a if args.workload.startswith("smooth") else b).step(args.steps)
+    elif args.workload == "riemann2048-ddf":
+        ddf_lattice(lks, inputs, workloads, dev, args.steps).step(args.steps)
     elif args.workload == "riemann2048":
         wl = workloads.RIEMANN_2048
         n = wl["nx"]

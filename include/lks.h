@@ -81,7 +81,35 @@ typedef enum {
 enum { LKS_D2Q9 = 9, LKS_D2Q25 = 25 };
 enum { LKS_F64 = 0, LKS_F32 = 1, LKS_BF16 = 2, LKS_F16 = 3 };
 enum { LKS_PERIODIC = 0, LKS_OUTFLOW = 1 };
-enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u };
+enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u, LKS_S_QE = 16u };
+
+/* Kinetic model of a D2Q25 lattice (D2Q9 is always LKS_MODEL_BGK).
+ *   LKS_MODEL_BGK  one distribution f (translational degrees of freedom only,
+ *                  gamma = 2 in 2D), BGK collision, tau = mu/(rho T).
+ *   LKS_MODEL_DDF  the double distribution of Sec. II.A.1-2: f carries mass,
+ *                  momentum and translational energy, g the internal energy
+ *                  of the non-translational degrees of freedom, g^eq =
+ *                  (C_v - D/2) T f^eq (eq. energy_eq_1_rykov), C_v = 1/(gamma-1)
+ *                  (R = 1), total energy E = sum g + sum |v|^2/2 f =
+ *                  rho (C_v T + |u|^2/2).  Quasi-equilibrium collision with the
+ *                  heat flux quasi-conserved (Pr <= 1, eq. new_collision_fi):
+ *                  Omega = -(f - f*)/tau1 - (f* - f^eq)/tau2, likewise for g,
+ *                  tau1 = mu/(rho T), tau2 = tau1/Pr; f* = f^eq + w_i (q_f . v_i)
+ *                  (|v_i|^2/4 - 1) with the translational heat flux q_f =
+ *                  1/2 sum |v - u|^2 (v - u) f, g* = g^eq + w_i (q_g . v_i) with
+ *                  q_g = sum (v - u) g.  Both distributions take the same van
+ *                  Leer fluxes.  State [50][ny][nx]: f deviations f_i - w_i rho0
+ *                  (planes 0..24), then g deviations g_i - (C_v - 1) w_i rho0
+ *                  (planes 25..49).  Five sensor planes: 0 S_KL = |sum f
+ *                  ln(f/f^eq)| + |sum g ln(g/g^eq)|, 1 S_NEQ = sum |f^neq| +
+ *                  sum |g^neq|, 2 S_PI of f, 3 S_Q = |sum v g^neq + sum v |v|^2/2
+ *                  f^neq|, 4 S_QE = sum |f* - f^eq| + sum |g* - g^eq| (eqs.
+ *                  HKL-sensor, sensor-neq-kin, sensor-TauNS-kin,
+ *                  sensor-qNSF-kin-ryk, Sensor-qe-kin); S_QE drives flag bit
+ *                  LKS_S_QE with thresholds thr_qe.  A positivity fault is any
+ *                  f, f^eq, g or g^eq not > 0.  The energy sum is E.  F32 or
+ *                  F64 storage, fused steps, no extension sensors. */
+enum { LKS_MODEL_BGK = 0, LKS_MODEL_DDF = 1 };
 
 /* Extension sensors (bit k of ext_mask), the rest of Table I evaluated on the
  * f distribution in the same pass, on the pre-collision populations; BGK
@@ -139,10 +167,16 @@ typedef struct {
     int32_t ext_reserved; /* must be 0                                          */
     double thr_ext[LKS_MAX_EXT][2]; /* (theta1 <= theta2) per extension sensor,
                              used when its LKS_FLAG_X bit is in flag_mask      */
+    int32_t model;        /* LKS_MODEL_BGK (0) or, on D2Q25, LKS_MODEL_DDF     */
+    int32_t model_reserved; /* must be 0                                        */
+    double gamma;         /* LKS_MODEL_DDF: adiabatic exponent, 1 < gamma < 2  */
+    double prandtl;       /* LKS_MODEL_DDF: Prandtl number, 0 < Pr <= 1        */
+    double thr_qe[2];     /* LKS_MODEL_DDF: (theta1 <= theta2) of S_QE         */
 } lks_config;
 
 typedef struct {
-    void* pop[2];         /* [Q][ny][nx] dtype, ping-pong state buffers        */
+    void* pop[2];         /* [Q][ny][nx] dtype, ping-pong state buffers (Q = 50
+                             with LKS_MODEL_DDF)                               */
     void* sensors;        /* [lks_sensor_planes(cfg)][ny][nx] float (double for
                              F64): base planes, then the extension planes     */
     uint8_t* flags;       /* [ny][nx]                                          */
@@ -155,7 +189,8 @@ typedef struct {
  * sums and counters).  0 for an invalid configuration. */
 size_t lks_scratch_bytes(const lks_config* cfg);
 
-/* Number of base sensor planes of a lattice (3 for D2Q9, 4 for D2Q25), 0 if invalid. */
+/* Number of base sensor planes of a lattice with the BGK model (3 for D2Q9,
+ * 4 for D2Q25), 0 if invalid; LKS_MODEL_DDF has 5 (lks_sensor_planes). */
 int32_t lks_num_sensors(int32_t lattice);
 
 /* Sensor planes a configuration writes: the base planes plus one per
@@ -168,8 +203,9 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
                       lks_ctx** out);
 
 /* Fill pop[0] with the equilibrium of the given FP64 device fields [ny][nx]
- * (the equilibrium initial condition of Sec. IV); T may be NULL on D2Q9
- * (isothermal) and is required on D2Q25.  Resets the step count to 0. */
+ * (the equilibrium initial condition of Sec. IV; with LKS_MODEL_DDF f^eq and
+ * g^eq); T may be NULL on D2Q9 (isothermal) and is required on D2Q25.
+ * Resets the step count to 0. */
 lks_status lks_init_equilibrium(lks_ctx* ctx, const double* rho, const double* ux,
                                 const double* uy, const double* T);
 

@@ -20,10 +20,39 @@
 // workgroups so that the eight XCDs each sweep their own band of tile
 // columns row by row: vertically adjacent tiles run on the same XCD shortly
 // after one another, so halo rows are served by that XCD's L2.
+//
+// The double distribution (f, g; quasi-equilibrium collision) has its own
+// kernel further down: the same fluxes on 50 planes, two passes over the
+// velocities (non-equilibrium parts and heat fluxes, then collision and
+// fluxes) and five sensors.
 #include "lks_device.h"
 #include "lks_internal.h"
 
+// Double distribution: 1 = stage f, then g, through one 25-plane LDS buffer
+// (own-cell values held in registers); 0 = stage all 50 planes at once.
+#ifndef LKS_DDF_SEQ
+#define LKS_DDF_SEQ 1
+#endif
+// its FP32 workgroup tile (cells) and minimum waves per SIMD (0 = compiler)
+#ifndef LKS_DDF_TX
+#define LKS_DDF_TX 32
+#endif
+#ifndef LKS_DDF_TY
+#define LKS_DDF_TY 4
+#endif
+#ifndef LKS_DDF_WAVES
+#define LKS_DDF_WAVES 0
+#endif
+
 namespace lks {
+
+// an opaque copy that is neither merged with another nor moved across other
+// side effects (volatile asm): forces a recomputation at this point
+template <typename T> __device__ __forceinline__ T fresh(T v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 // GH5 nodes (x-node a, y-node b), He_n(xi)/n! and 1D weights, T_ref = 1
 __device__ __forceinline__ constexpr double gh5_xi(int a)
@@ -387,6 +416,543 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
     block_sums_n<NT / kWave>(acc, partials + (long long)blockIdx.x * kNsums);
 }
 
+// ---------------------------------------------------------------------------
+// Double distribution (f, g) on the 25-velocity lattice with the
+// quasi-equilibrium collision (Sec. II.A.1-3, eqs. new_collision_fi,
+// finalDiscretePDE): f carries mass, momentum and translational energy, g the
+// non-translational internal energy, g^eq = (C_v - D/2) T f^eq (eq.
+// energy_eq_1_rykov), E = sum (g + |v|^2/2 f) = rho (C_v T + |u|^2/2).  With
+// the heat flux quasi-conserved (Pr <= 1): f* = f^eq + w (q_f . v)(|v|^2/4 - 1)
+// (Grad heat-flux term of the translational heat flux q_f of f), g* = g^eq +
+// w (q_g . v) (q_g = sum (v - u) g), Omega = -(f - f*)/tau1 - (f* - f^eq)/tau2,
+// tau1 = mu/(rho T), tau2 = tau1/Pr.  Both distributions take the same van
+// Leer fluxes.  Sensors: |sum f ln(f/f^eq)| + |sum g ln(g/g^eq)|, sum |f^neq| +
+// sum |g^neq|, S_PI of f, |sum v g^neq + sum v |v|^2/2 f^neq|, and the QE
+// sensor sum |f* - f^eq| + sum |g* - g^eq| (eqs. HKL-sensor, sensor-neq-kin,
+// sensor-TauNS-kin, sensor-qNSF-kin-ryk, Sensor-qe-kin).
+// Storage: [50][ny][nx], f deviations from w rho0, then g deviations from
+// (C_v - 1) w rho0.
+// ---------------------------------------------------------------------------
+template <typename S, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void d2q25_ddf_kernel(D2Q25Args a,
+                                                       const typename Store<S>::raw* __restrict__ fin,
+                                                       typename Store<S>::raw* __restrict__ fout,
+                                                       typename Store<S>::real* __restrict__ sens,
+                                                       uint8_t* __restrict__ flags,
+                                                       double* __restrict__ partials,
+                                                       unsigned long long* __restrict__ faults)
+{
+    using R = typename Store<S>::real;
+    using T = Tile<TX, TY>;
+    constexpr int NT = TX * TY;
+    __shared__ R lds[50 * T::kPlane];
+
+    const int nx = a.nx, ny = a.ny;
+    const long long plane = a.plane;
+    int tile_x, tile_y;
+    {
+        const int b = blockIdx.x;
+        if (a.tiles_x % 8 == 0) {
+            const int bw = a.tiles_x / 8, l = b / 8;
+            tile_x = (b % 8) * bw + l % bw;
+            tile_y = l / bw;
+        } else {
+            tile_x = b % a.tiles_x;
+            tile_y = b / a.tiles_x;
+        }
+    }
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int X0 = tile_x * TX, Y0 = tile_y * TY;
+    const int X = X0 + tx, Y = Y0 + ty;
+    const bool active = X < nx && Y < ny;
+    const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
+
+    constexpr int HR = (4 * TX + NT - 1) / NT;
+    long long own = (long long)gyc * nx + gxc;
+    long long hoff[HR];
+    int hlds[HR];
+#pragma unroll
+    for (int k = 0; k < HR; ++k) {
+        const int h = threadIdx.x + k * NT;
+        const int hr = h / TX, c = h % TX;
+        const int r = hr < 2 ? hr - 2 : TY + hr - 2;
+        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
+    }
+    long long coff = 0;
+    int clds = -1;
+    if (threadIdx.x < 4 * TY) {
+        const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
+        const int c = hc < 2 ? hc - 2 : TX + hc - 2;
+        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        clds = T::rowbase(r) + c;
+    }
+    const int olds = T::rowbase(ty) + tx;
+
+    // ---- stage the 50 planes (f, then g) and accumulate the moments the
+    //      equilibria need: sum d, sum v d, sum |v|^2 d of f and sum dg of g
+    const R rho0 = R(a.rho0);
+    const R cv = R(a.cv);
+    R drho = R(0), jx = R(0), jy = R(0), m2 = R(0), dg0 = R(0);
+    // one distribution at a time keeps only 25 planes' loads in flight
+#pragma nounroll
+    for (int dist = 0; dist < 2; ++dist) {
+        R vin[25], vh[HR][25], vc[25];
+        sfor25<25>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const typename Store<S>::raw* src = fin + (25 * dist + i) * plane;
+            vin[i] = Store<S>::to_real(src[own]);
+#pragma unroll
+            for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
+            vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
+        });
+        sfor25<25>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int ia = i / 5, ib = i % 5;
+            R* dst = lds + (25 * dist + i) * T::kPlane;
+            const R v = vin[i];
+            dst[olds] = v;
+#pragma unroll
+            for (int k = 0; k < HR; ++k)
+                if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];
+            if (clds >= 0) dst[clds] = vc[i];
+            if (dist == 0) {
+                drho += v;
+                if (ia != 2) jx += R(gh5_xi(ia)) * v;
+                if (ib != 2) jy += R(gh5_xi(ib)) * v;
+                m2 += R(gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) * v;
+            } else {
+                dg0 += v;
+            }
+        });
+    }
+    __syncthreads();
+
+    // ---- cell state
+    const R rho = rho0 + drho;
+    const R irho = R(1) / rho;
+    const R ux = jx * irho, uy = jy * irho;
+    // C_v (T - 1) = (E - C_v rho)/rho - |u|^2/2 with E - C_v rho = dg0 + m2/2
+    // - C_v drho (sum_i w_i = 1, sum_i w_i |v_i|^2/2 = 1: the reference parts cancel)
+    const R tm1 = ((dg0 + R(0.5) * m2 - cv * drho) * irho - R(0.5) * (ux * ux + uy * uy)) / cv;
+    const R Tc = R(1) + tm1;
+    const R gfac = cv - R(1);                              // g^eq = (C_v - 1) T f^eq
+    const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
+                       T::rowbase(ty + 2)};
+    const int own_lds = rb[2] + tx;
+
+    // ---- pass 1: non-equilibrium parts of f and g: the sensors and the heat
+    //      fluxes q_f = 1/2 sum |c|^2 c f^neq, q_g = sum c g^neq (c = v - u; the
+    //      equilibria carry none, so the non-equilibrium parts give them
+    //      without cancellation)
+    R klf = R(0), klg = R(0), gsum = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0),
+      qy = R(0), qfx = R(0), qfy = R(0), qgx = R(0), qgy = R(0);
+    // positivity (f, f^eq, g, g^eq > 0) and the reach of the KL series,
+    // tested per population (lane masks, no values kept for later)
+    bool nonpos = false, far = false;
+    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+        const int i = 5 * ia + ib;
+        const R w = R(gh5_w(ia) * gh5_w(ib));
+        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+        const R d = lds[i * T::kPlane + own_lds], dg = lds[(25 + i) * T::kPlane + own_lds];
+        const R fneq = d - deq;
+        const R feq = w * rho0 + deq;
+        const R x = fneq * rcp(feq);
+        // deviation of g^eq from (C_v - 1) w rho0: (C_v - 1)(T deq + (T - 1) w rho0)
+        const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
+        const R gneq = dg - dgeq;
+        const R geq = gfac * (w * rho0) + dgeq;
+        const R y = gneq * rcp(geq);
+        klf += (fneq * x) * kl_series(x);
+        klg += (gneq * y) * kl_series(y);
+        gsum += gneq;
+        nonpos |= !(feq > R(0)) | !(geq > R(0)) | !(x > R(-1)) | !(y > R(-1));
+        far |= !(fabs(x) <= KlCut<R>::v) | !(fabs(y) <= KlCut<R>::v);
+        neq += fabs(fneq) + fabs(gneq);
+        pxx += vx * vx * fneq;
+        pxy += vx * vy * fneq;
+        pyy += vy * vy * fneq;
+        const R e = R(0.5) * (vx * vx + vy * vy);
+        qx += vx * (gneq + e * fneq);
+        qy += vy * (gneq + e * fneq);
+        const R cx = vx - ux, cy = vy - uy;
+        const R hc = R(0.5) * (cx * cx + cy * cy) * fneq;
+        qfx += hc * cx;
+        qfy += hc * cy;
+        qgx += cx * gneq;
+        qgy += cy * gneq;
+    });
+    if (far) {
+        // rare: some population far from equilibrium (or NaN): the closed form
+        klf = R(0);
+        klg = R(0);
+        d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+            const int i = 5 * ia + ib;
+            const R w = R(gh5_w(ia) * gh5_w(ib));
+            const R d = lds[i * T::kPlane + own_lds], dg = lds[(25 + i) * T::kPlane + own_lds];
+            const R feq = w * rho0 + deq;
+            const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
+            const R geq = gfac * (w * rho0) + dgeq;
+            klf += feq * kl_phi((d - deq) * rcp(feq));
+            klg += geq * kl_phi((dg - dgeq) * rcp(geq));
+            // one population at a time: the rare path must not set the
+            // kernel's register budget
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+
+    // ---- pass 2: quasi-equilibrium collision and van Leer fluxes.
+    //      f' = f - A div - (dt/tau1)(f - f^eq) + (dt/tau1 - dt/tau2)(f* - f^eq)
+    const R A = R(a.dt / a.dx);
+    const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
+    const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
+    const long long off = (long long)Y * nx + X;
+    R qe = R(0);
+    auto div_of = [&](const R* t, R d, int ia, int ib, R vx, R vy) {
+        R div = R(0);
+        if (ia != 2) {
+            const R* row = t + own_lds;
+            div += vx * (ia > 2 ? flux_diff<R, 1>(row[-2], row[-1], d, row[1], R(0))
+                                : flux_diff<R, -1>(R(0), row[-1], d, row[1], row[2]));
+        }
+        if (ib != 2) {
+            div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
+                                : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
+        }
+        return div;
+    };
+    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+        const int i = 5 * ia + ib;
+        const R w = R(gh5_w(ia) * gh5_w(ib));
+        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+        const R* tf = lds + i * T::kPlane;
+        const R* tg = lds + (25 + i) * T::kPlane;
+        const R d = tf[own_lds], dg = tg[own_lds];
+        const R fneq = d - deq;
+        const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
+        // f* - f^eq = w (q_f . v)(|v|^2/4 - 1), g* - g^eq = w (q_g . v)
+        const R dfs = w * (qfx * vx + qfy * vy) * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
+        const R dgs = w * (qgx * vx + qgy * vy);
+        qe += fabs(dfs) + fabs(dgs);
+        const R divf = div_of(tf, d, ia, ib, vx, vy);
+        const R divg = div_of(tg, dg, ia, ib, vx, vy);
+        if (active) {
+            fout[i * plane + off] = Store<S>::from_real(d - A * divf - B1 * fneq + B12 * dfs);
+            fout[(25 + i) * plane + off] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
+        }
+    });
+    // sum f ln(f/f^eq) = sum f^eq phi(x) (f and f^eq carry the same mass);
+    // sum g ln(g/g^eq) = sum g^eq phi(y) + sum g^neq
+    const R klsum = fabs(klf) + fabs(klg + gsum);
+    const bool fault = nonpos || !(klsum == klsum);
+    const R s_kl = fault ? R(INFINITY) : klsum;
+    const R s_pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+    const R s_q = sqrt(qx * qx + qy * qy);
+    double acc[kNsums];
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
+    if (active) {
+        const R sv[5] = {s_kl, neq, s_pi, s_q, qe};
+        int level = 0;
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            if (a.mask & (1u << s)) {
+                const R t0 = s < 4 ? R(a.thr[s][0]) : R(a.thr_qe[0]);
+                const R t1 = s < 4 ? R(a.thr[s][1]) : R(a.thr_qe[1]);
+                const int l = (sv[s] > t0) + (sv[s] > t1);
+                level = l > level ? l : level;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 5; ++s) sens[s * plane + off] = sv[s];
+        flags[off] = fault ? uint8_t(0x82) : uint8_t(level);
+        if (fault) atomicAdd(faults, 1ull);
+        acc[0] = (double)drho;
+        acc[1] = (double)jx;
+        acc[2] = (double)jy;
+        acc[3] = (double)dg0 + 0.5 * (double)m2;     // E - C_v rho0
+        acc[4] = (double)s_kl;
+        acc[5] = (double)neq;
+        acc[6] = (double)s_pi;
+        acc[7] = (double)s_q;
+    }
+    block_sums_n<NT / kWave>(acc, partials + (long long)blockIdx.x * kNsums);
+}
+
+// The same step with f and g staged one after the other through a 25-plane
+// LDS buffer (half the LDS of staging both, so more workgroups per CU): the
+// own-cell values of f and g stay in registers; f is staged with its halo,
+// the moments, pass 1 and the f update run, then g is staged into the same
+// buffer and updated.  Same arithmetic as d2q25_ddf_kernel.
+#if LKS_DDF_WAVES > 0
+#define LKS_DDF_ATTR __attribute__((amdgpu_waves_per_eu(LKS_DDF_WAVES)))
+#else
+#define LKS_DDF_ATTR
+#endif
+template <typename S, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_seq_kernel(
+    D2Q25Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
+    typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ partials,
+    unsigned long long* __restrict__ faults)
+{
+    using R = typename Store<S>::real;
+    using T = Tile<TX, TY>;
+    constexpr int NT = TX * TY;
+    __shared__ R lds[25 * T::kPlane];
+
+    const int nx = a.nx, ny = a.ny;
+    const long long plane = a.plane;
+    int tile_x, tile_y;
+    {
+        const int b = blockIdx.x;
+        if (a.tiles_x % 8 == 0) {
+            const int bw = a.tiles_x / 8, l = b / 8;
+            tile_x = (b % 8) * bw + l % bw;
+            tile_y = l / bw;
+        } else {
+            tile_x = b % a.tiles_x;
+            tile_y = b / a.tiles_x;
+        }
+    }
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int X0 = tile_x * TX, Y0 = tile_y * TY;
+    const int X = X0 + tx, Y = Y0 + ty;
+    const bool active = X < nx && Y < ny;
+    const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
+
+    constexpr int HR = (4 * TX + NT - 1) / NT;
+    const long long own = (long long)gyc * nx + gxc;
+    long long hoff[HR];
+    int hlds[HR];
+#pragma unroll
+    for (int k = 0; k < HR; ++k) {
+        const int h = threadIdx.x + k * NT;
+        const int hr = h / TX, c = h % TX;
+        const int r = hr < 2 ? hr - 2 : TY + hr - 2;
+        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
+    }
+    long long coff = 0;
+    int clds = -1;
+    if (threadIdx.x < 4 * TY) {
+        const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
+        const int c = hc < 2 ? hc - 2 : TX + hc - 2;
+        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        clds = T::rowbase(r) + c;
+    }
+    const int olds = T::rowbase(ty) + tx;
+    const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
+                       T::rowbase(ty + 2)};
+    const int own_lds = rb[2] + tx;
+
+    // stage planes [p0, p0 + 25) with their halo; own-cell values into own_v
+    auto stage = [&](int p0, R (&own_v)[25], bool own_loaded) {
+        R vh[HR][25], vc[25];
+        sfor25<25>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const typename Store<S>::raw* src = fin + (p0 + i) * plane;
+            if (!own_loaded) own_v[i] = Store<S>::to_real(src[own]);
+#pragma unroll
+            for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
+            vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
+        });
+        sfor25<25>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            R* dst = lds + i * T::kPlane;
+            dst[olds] = own_v[i];
+#pragma unroll
+            for (int k = 0; k < HR; ++k)
+                if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];
+            if (clds >= 0) dst[clds] = vc[i];
+        });
+    };
+
+    // ---- own-cell g values, then f staged with its halo
+    R fc[25], gc[25];
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        gc[i] = Store<S>::to_real(fin[(25 + i) * plane + own]);
+    });
+    stage(0, fc, false);
+
+    // ---- moments: sum d, sum v d, sum |v|^2 d of f and sum dg of g
+    const R rho0 = R(a.rho0);
+    const R cv = R(a.cv);
+    R drho = R(0), jx = R(0), jy = R(0), m2 = R(0), dg0 = R(0);
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ia = i / 5, ib = i % 5;
+        const R v = fc[i];
+        drho += v;
+        if (ia != 2) jx += R(gh5_xi(ia)) * v;
+        if (ib != 2) jy += R(gh5_xi(ib)) * v;
+        m2 += R(gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) * v;
+        dg0 += gc[i];
+    });
+    const R rho = rho0 + drho;
+    const R irho = R(1) / rho;
+    const R ux = jx * irho, uy = jy * irho;
+    const R tm1 = ((dg0 + R(0.5) * m2 - cv * drho) * irho - R(0.5) * (ux * ux + uy * uy)) / cv;
+    const R Tc = R(1) + tm1;
+    const R gfac = cv - R(1);
+
+    __syncthreads();
+
+    // ---- pass 1: sensors and the heat fluxes of f and g (as d2q25_ddf_kernel);
+    //      f's own-cell values are read back from the staged buffer
+    R klf = R(0), klg = R(0), gsum = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0),
+      qy = R(0), qfx = R(0), qfy = R(0), qgx = R(0), qgy = R(0);
+    // positivity (f, f^eq, g, g^eq > 0) and the reach of the KL series,
+    // tested per population (lane masks, no values kept for later)
+    bool nonpos = false, far = false;
+    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+        const int i = 5 * ia + ib;
+        const R w = R(gh5_w(ia) * gh5_w(ib));
+        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+        const R fneq = lds[i * T::kPlane + own_lds] - deq;
+        const R feq = w * rho0 + deq;
+        const R x = fneq * rcp(feq);
+        const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
+        const R gneq = gc[i] - dgeq;
+        const R geq = gfac * (w * rho0) + dgeq;
+        const R y = gneq * rcp(geq);
+        klf += (fneq * x) * kl_series(x);
+        klg += (gneq * y) * kl_series(y);
+        gsum += gneq;
+        nonpos |= !(feq > R(0)) | !(geq > R(0)) | !(x > R(-1)) | !(y > R(-1));
+        far |= !(fabs(x) <= KlCut<R>::v) | !(fabs(y) <= KlCut<R>::v);
+        neq += fabs(fneq) + fabs(gneq);
+        pxx += vx * vx * fneq;
+        pxy += vx * vy * fneq;
+        pyy += vy * vy * fneq;
+        const R e = R(0.5) * (vx * vx + vy * vy);
+        qx += vx * (gneq + e * fneq);
+        qy += vy * (gneq + e * fneq);
+        const R cx = vx - ux, cy = vy - uy;
+        const R hc = R(0.5) * (cx * cx + cy * cy) * fneq;
+        qfx += hc * cx;
+        qfy += hc * cy;
+        qgx += cx * gneq;
+        qgy += cy * gneq;
+    });
+    // Each later pass recomputes the equilibria from opaque copies (fresh) of
+    // the moments: the compiler would otherwise keep pass 1's 25 values live
+    // through the passes instead of recomputing them (same arithmetic).
+    if (far) {
+        klf = R(0);
+        klg = R(0);
+        d2q25_deq<R>(fresh(drho), fresh(rho), fresh(ux), fresh(uy), fresh(tm1), [&](int ia, int ib, R deq) {
+            const int i = 5 * ia + ib;
+            const R w = R(gh5_w(ia) * gh5_w(ib));
+            const R feq = w * rho0 + deq;
+            const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
+            const R geq = gfac * (w * rho0) + dgeq;
+            klf += feq * kl_phi((lds[i * T::kPlane + own_lds] - deq) * rcp(feq));
+            klg += geq * kl_phi((gc[i] - dgeq) * rcp(geq));
+            // one population at a time: the rare path must not set the
+            // kernel's register budget
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+
+    // ---- pass 2: f, then g (the LDS buffer is reused)
+    const R A = R(a.dt / a.dx);
+    const R B1 = R(a.dt) * rho * Tc / R(a.mu);
+    const R B12 = B1 * (R(1) - R(a.prandtl));
+    const long long off = (long long)Y * nx + X;
+    auto div_of = [&](const R* t, R d, int ia, int ib, R vx, R vy) {
+        R div = R(0);
+        if (ia != 2) {
+            const R* row = t + own_lds;
+            div += vx * (ia > 2 ? flux_diff<R, 1>(row[-2], row[-1], d, row[1], R(0))
+                                : flux_diff<R, -1>(R(0), row[-1], d, row[1], row[2]));
+        }
+        if (ib != 2) {
+            div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
+                                : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
+        }
+        return div;
+    };
+    R qe = R(0);
+    d2q25_deq<R>(fresh(drho), fresh(rho), fresh(ux), fresh(uy), fresh(tm1), [&](int ia, int ib, R deq) {
+        const int i = 5 * ia + ib;
+        const R w = R(gh5_w(ia) * gh5_w(ib));
+        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+        const R d = lds[i * T::kPlane + own_lds];
+        const R fneq = d - deq;
+        const R dfs = w * (qfx * vx + qfy * vy) * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
+        qe += fabs(dfs);
+        const R divf = div_of(lds + i * T::kPlane, d, ia, ib, vx, vy);
+        if (active) fout[i * plane + off] = Store<S>::from_real(d - A * divf - B1 * fneq + B12 * dfs);
+    });
+    __syncthreads();              // every f read of the buffer is done
+    stage(25, gc, true);
+    __syncthreads();
+    d2q25_deq<R>(fresh(drho), fresh(rho), fresh(ux), fresh(uy), fresh(tm1), [&](int ia, int ib, R deq) {
+        const int i = 5 * ia + ib;
+        const R w = R(gh5_w(ia) * gh5_w(ib));
+        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+        const R dg = gc[i];
+        const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
+        const R dgs = w * (qgx * vx + qgy * vy);
+        qe += fabs(dgs);
+        const R divg = div_of(lds + i * T::kPlane, dg, ia, ib, vx, vy);
+        if (active) fout[(25 + i) * plane + off] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
+    });
+
+    const R klsum = fabs(klf) + fabs(klg + gsum);
+    const bool fault = nonpos || !(klsum == klsum);
+    const R s_kl = fault ? R(INFINITY) : klsum;
+    const R s_pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+    const R s_q = sqrt(qx * qx + qy * qy);
+    double acc[kNsums];
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
+    if (active) {
+        const R sv[5] = {s_kl, neq, s_pi, s_q, qe};
+        int level = 0;
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            if (a.mask & (1u << s)) {
+                const R t0 = s < 4 ? R(a.thr[s][0]) : R(a.thr_qe[0]);
+                const R t1 = s < 4 ? R(a.thr[s][1]) : R(a.thr_qe[1]);
+                const int l = (sv[s] > t0) + (sv[s] > t1);
+                level = l > level ? l : level;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 5; ++s) sens[s * plane + off] = sv[s];
+        flags[off] = fault ? uint8_t(0x82) : uint8_t(level);
+        if (fault) atomicAdd(faults, 1ull);
+        acc[0] = (double)drho;
+        acc[1] = (double)jx;
+        acc[2] = (double)jy;
+        acc[3] = (double)dg0 + 0.5 * (double)m2;     // E - C_v rho0
+        acc[4] = (double)s_kl;
+        acc[5] = (double)neq;
+        acc[6] = (double)s_pi;
+        acc[7] = (double)s_q;
+    }
+    block_sums_n<NT / kWave>(acc, partials + (long long)blockIdx.x * kNsums);
+}
+
+template <typename S, int TX, int TY>
+static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fout, void* sens,
+                                  uint8_t* flags, double* partials, unsigned long long* faults,
+                                  hipStream_t s)
+{
+    using raw = typename Store<S>::raw;
+    using R = typename Store<S>::real;
+    if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
+    if (LKS_DDF_SEQ)
+        d2q25_ddf_seq_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else
+        d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    return hipGetLastError();
+}
+
 template <typename S, int TX, int TY>
 static hipError_t launch_tile(const D2Q25Args& a, const void* fin, void* fout, void* sens, uint8_t* flags,
                               double* partials, unsigned long long* faults, hipStream_t s)
@@ -406,6 +972,13 @@ static hipError_t launch_tile(const D2Q25Args& a, const void* fin, void* fout, v
 hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fout, void* sens,
                         uint8_t* flags, double* partials, unsigned long long* faults, hipStream_t s)
 {
+    if (a.model == 1) {
+        switch (dtype) {
+        case 0: return launch_ddf_tile<double, 16, 4>(a, fin, fout, sens, flags, partials, faults, s);
+        case 1: return launch_ddf_tile<float, LKS_DDF_TX, LKS_DDF_TY>(a, fin, fout, sens, flags, partials, faults, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (dtype) {
     case 0: return launch_tile<double, 32, 2>(a, fin, fout, sens, flags, partials, faults, s);
     case 1: return launch_tile<float, 64, 4>(a, fin, fout, sens, flags, partials, faults, s);
@@ -413,9 +986,14 @@ hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fo
     }
 }
 
-// tile shape the launcher expects for a storage type
-void d2q25_tile_shape(int dtype, int* tx, int* ty)
+// tile shape the launcher expects for a storage type and model
+void d2q25_tile_shape(int dtype, int model, int* tx, int* ty)
 {
+    if (model == 1) {
+        *tx = dtype == 0 ? 16 : LKS_DDF_TX;
+        *ty = dtype == 0 ? 4 : LKS_DDF_TY;
+        return;
+    }
     *tx = dtype == 0 ? 32 : 64;
     *ty = dtype == 0 ? 2 : 4;
 }
@@ -462,6 +1040,81 @@ __global__ __launch_bounds__(kBlock) void d2q25_moments_kernel(long long n, doub
     ux[c] = u;
     uy[c] = v;
     if (T) T[c] = 1.0 + (edev - drho) / r - 0.5 * (u * u + v * v);
+}
+
+// double distribution: f^eq and g^eq = (C_v - 1) T f^eq as deviations
+template <typename S>
+__global__ __launch_bounds__(kBlock) void d2q25_ddf_init_kernel(long long n, double rho0, double cv,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ ux,
+                                                           const double* __restrict__ uy,
+                                                           const double* __restrict__ T,
+                                                           typename Store<S>::raw* __restrict__ pop)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    const double r = rho[c], t = T[c];
+    d2q25_deq<double>(r - rho0, r, ux[c], uy[c], t - 1.0, [&](int ia, int ib, double deq) {
+        const int i = 5 * ia + ib;
+        const double w = gh5_w(ia) * gh5_w(ib);
+        pop[i * n + c] = Store<S>::from_real((typename Store<S>::real)deq);
+        const double dgeq = (cv - 1.0) * (t * deq + (t - 1.0) * w * rho0);
+        pop[(25 + i) * n + c] = Store<S>::from_real((typename Store<S>::real)dgeq);
+    });
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void d2q25_ddf_moments_kernel(long long n, double rho0, double cv,
+                                                              const typename Store<S>::raw* __restrict__ pop,
+                                                              double* __restrict__ rho,
+                                                              double* __restrict__ ux,
+                                                              double* __restrict__ uy,
+                                                              double* __restrict__ T)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    double drho = 0.0, jx = 0.0, jy = 0.0, m2 = 0.0, dg0 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 25; ++i) {
+        const double d = (double)Store<S>::to_real(pop[i * n + c]);
+        const double vx = gh5_xi(i / 5), vy = gh5_xi(i % 5);
+        drho += d;
+        jx += vx * d;
+        jy += vy * d;
+        m2 += (vx * vx + vy * vy) * d;
+        dg0 += (double)Store<S>::to_real(pop[(25 + i) * n + c]);
+    }
+    const double r = rho0 + drho;
+    const double u = jx / r, v = jy / r;
+    rho[c] = r;
+    ux[c] = u;
+    uy[c] = v;
+    if (T) T[c] = 1.0 + ((dg0 + 0.5 * m2 - cv * drho) / r - 0.5 * (u * u + v * v)) / cv;
+}
+
+hipError_t launch_d2q25_ddf_init(int dtype, long long n, double rho0, double cv, const double* rho,
+                                 const double* ux, const double* uy, const double* T, void* pop,
+                                 hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    switch (dtype) {
+    case 0: d2q25_ddf_init_kernel<double><<<grid, block, 0, s>>>(n, rho0, cv, rho, ux, uy, T, (double*)pop); break;
+    case 1: d2q25_ddf_init_kernel<float><<<grid, block, 0, s>>>(n, rho0, cv, rho, ux, uy, T, (float*)pop); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_d2q25_ddf_moments(int dtype, long long n, double rho0, double cv, const void* pop,
+                                    double* rho, double* ux, double* uy, double* T, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    switch (dtype) {
+    case 0: d2q25_ddf_moments_kernel<double><<<grid, block, 0, s>>>(n, rho0, cv, (const double*)pop, rho, ux, uy, T); break;
+    case 1: d2q25_ddf_moments_kernel<float><<<grid, block, 0, s>>>(n, rho0, cv, (const float*)pop, rho, ux, uy, T); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_d2q25_init(int dtype, long long n, double rho0, const double* rho, const double* ux,

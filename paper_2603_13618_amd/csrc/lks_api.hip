@@ -20,13 +20,18 @@ thread_local std::string g_create_err;
 
 int q_of(int lattice) { return lattice == LKS_D2Q9 ? 9 : (lattice == LKS_D2Q25 ? 25 : 0); }
 int nsens_of(int lattice) { return lattice == LKS_D2Q9 ? 3 : (lattice == LKS_D2Q25 ? 4 : 0); }
+bool ddf(const lks_config& c) { return c.model == LKS_MODEL_DDF; }
+// stored planes of the state and base sensor planes of a configuration
+int state_planes(const lks_config& c) { return ddf(c) ? 50 : q_of(c.lattice); }
+int base_planes(const lks_config& c) { return ddf(c) ? 5 : nsens_of(c.lattice); }
+double cv_of(const lks_config& c) { return 1.0 / (c.gamma - 1.0); }
 
 // extension sensors: planes after the base planes, in increasing bit order
 lks::ExtArgs ext_args(const lks_config& c)
 {
     lks::ExtArgs x;
     x.mask = c.ext_mask;
-    int p = nsens_of(c.lattice);
+    int p = base_planes(c);
     for (int k = 0; k < lks::kNumExtHost; ++k) {
         x.plane[k] = (c.ext_mask & (1u << k)) ? p++ : -1;
         for (int j = 0; j < 2; ++j) {
@@ -37,7 +42,7 @@ lks::ExtArgs ext_args(const lks_config& c)
     return x;
 }
 
-int planes_of(const lks_config& c) { return nsens_of(c.lattice) + __builtin_popcount(c.ext_mask); }
+int planes_of(const lks_config& c) { return base_planes(c) + __builtin_popcount(c.ext_mask); }
 size_t store_bytes(int dtype) { return dtype == LKS_F64 ? 8 : (dtype == LKS_F32 ? 4 : 2); }
 size_t sens_bytes(int dtype) { return dtype == LKS_F64 ? 8 : 4; }
 int wide_vec(int dtype) { return dtype == LKS_F64 ? 2 : 4; }
@@ -82,7 +87,17 @@ const char* validate_config(const lks_config* c)
     const unsigned valid_ext = c->lattice == LKS_D2Q9 ? all_ext & ~(unsigned)LKS_X_QF
                                                       : all_ext & ~(unsigned)(LKS_X_COMP | LKS_X_STRAIN);
     if (c->ext_mask & ~valid_ext) return "ext_mask names a sensor this lattice does not have";
-    const unsigned valid = (c->lattice == LKS_D2Q9 ? 7u : 15u) | (c->ext_mask << 8);
+    if (c->model != LKS_MODEL_BGK && c->model != LKS_MODEL_DDF) return "model must be BGK or DDF";
+    if (c->model_reserved != 0) return "model_reserved must be 0";
+    if (c->model == LKS_MODEL_DDF) {
+        if (c->lattice != LKS_D2Q25) return "the double distribution needs D2Q25";
+        if (!(c->gamma > 1.0 && c->gamma < 2.0)) return "gamma must be in (1, 2)";
+        if (!(c->prandtl > 0.0 && c->prandtl <= 1.0)) return "prandtl must be in (0, 1]";
+        if (std::isnan(c->thr_qe[0]) || std::isnan(c->thr_qe[1])) return "threshold is NaN";
+        if (c->thr_qe[0] > c->thr_qe[1]) return "thresholds must satisfy theta1 <= theta2";
+    }
+    const unsigned base = c->lattice == LKS_D2Q9 ? 7u : (c->model == LKS_MODEL_DDF ? 31u : 15u);
+    const unsigned valid = base | (c->ext_mask << 8);
     if (c->flag_mask & ~valid) return "flag_mask names a sensor this configuration does not compute";
     for (int s = 0; s < LKS_MAX_SENSORS; ++s) {
         if (std::isnan(c->thr[s][0]) || std::isnan(c->thr[s][1])) return "threshold is NaN";
@@ -122,7 +137,12 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
     std::memcpy(a.thr, c.thr, sizeof(a.thr));
     a.mask = c.flag_mask;
     a.x = ext_args(c);
-    lks::d2q25_tile_shape(c.dtype, &a.tile_x, &a.tile_y);
+    a.model = c.model;
+    a.cv = ddf(c) ? cv_of(c) : 0.0;
+    a.prandtl = ddf(c) ? c.prandtl : 1.0;
+    a.thr_qe[0] = ddf(c) ? c.thr_qe[0] : 0.0;
+    a.thr_qe[1] = ddf(c) ? c.thr_qe[1] : 0.0;
+    lks::d2q25_tile_shape(c.dtype, c.model, &a.tile_x, &a.tile_y);
     a.tiles_x = (c.nx + a.tile_x - 1) / a.tile_x;
     a.tiles_y = (c.ny + a.tile_y - 1) / a.tile_y;
     a.nblocks = a.tiles_x * a.tiles_y;
@@ -217,6 +237,8 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
         return fail(nullptr, LKS_EUNSUPPORTED, "D2Q25 supports F32 and F64 storage");
     if (cfg->ext_mask && cfg->dtype != LKS_F32 && cfg->dtype != LKS_F64)
         return fail(nullptr, LKS_EUNSUPPORTED, "extension sensors need F32 or F64 storage");
+    if (cfg->ext_mask && ddf(*cfg))
+        return fail(nullptr, LKS_EUNSUPPORTED, "extension sensors are BGK-model only");
     if (!buf->pop[0] || !buf->pop[1] || !buf->sensors || !buf->flags || !buf->sums || !buf->scratch)
         return fail(nullptr, LKS_EINVAL, "a buffer pointer is NULL");
     if (buf->pop[0] == buf->pop[1]) return fail(nullptr, LKS_EINVAL, "pop[0] and pop[1] alias");
@@ -236,7 +258,7 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     c->cfg = *cfg;
     c->buf = *buf;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    c->Q = q_of(cfg->lattice);
+    c->Q = state_planes(*cfg);
     c->nsens = planes_of(*cfg);
     c->n = (long long)cfg->nx * cfg->ny;
     c->cur = 0;
@@ -278,7 +300,10 @@ lks_status lks_init_equilibrium(lks_ctx* c, const double* rho, const double* ux,
     if (!c) return LKS_EINVAL;
     if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
     if (c->cfg.lattice == LKS_D2Q25 && !T) return fail(c, LKS_EINVAL, "T is required on D2Q25");
-    hipError_t e = c->cfg.lattice == LKS_D2Q25
+    hipError_t e = ddf(c->cfg)
+                       ? lks::launch_d2q25_ddf_init(c->cfg.dtype, c->n, c->cfg.rho0, cv_of(c->cfg), rho,
+                                                    ux, uy, T, c->buf.pop[0], c->stream)
+                   : c->cfg.lattice == LKS_D2Q25
                        ? lks::launch_d2q25_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy, T,
                                                 c->buf.pop[0], c->stream)
                        : lks::launch_d2q9_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy,
@@ -344,7 +369,9 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
             if (lks_status st = hip_check(c, e, "step kernel")) return st;
         }
         const double mass_ref = (double)c->n * c->cfg.rho0;
-        const double energy_ref = q25 ? mass_ref : 0.0;   // sum_i w_i |v_i|^2 / 2 = 1 on D2Q25
+        // sum_i w_i |v_i|^2 / 2 = 1 on D2Q25; the double distribution adds
+        // (C_v - 1) rho0 of g per cell
+        const double energy_ref = !q25 ? 0.0 : (ddf(c->cfg) ? cv_of(c->cfg) * mass_ref : mass_ref);
         hipError_t e = lks::launch_finalize(c->partials, nb, m, c->buf.sums, c->steps,
                                             c->cfg.max_steps, mass_ref, energy_ref, c->stream);
         if (lks_status st = hip_check(c, e, "finalize kernel")) return st;
@@ -367,7 +394,10 @@ lks_status lks_moments(lks_ctx* c, double* rho, double* ux, double* uy, double* 
     if (!c) return LKS_EINVAL;
     if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
     if (!c->ready) return fail(c, LKS_ESTATE, "moments before init_equilibrium or restore");
-    hipError_t e = c->cfg.lattice == LKS_D2Q25
+    hipError_t e = ddf(c->cfg)
+                       ? lks::launch_d2q25_ddf_moments(c->cfg.dtype, c->n, c->cfg.rho0, cv_of(c->cfg),
+                                                       c->buf.pop[c->cur], rho, ux, uy, T, c->stream)
+                   : c->cfg.lattice == LKS_D2Q25
                        ? lks::launch_d2q25_moments(c->cfg.dtype, c->n, c->cfg.rho0,
                                                    c->buf.pop[c->cur], rho, ux, uy, T, c->stream)
                        : lks::launch_d2q9_moments(c->cfg.dtype, c->n, c->cfg.rho0,

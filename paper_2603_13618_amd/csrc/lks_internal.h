@@ -58,6 +58,11 @@ struct D2Q25Args {
     int tiles_x, tiles_y;
     int nblocks;
     ExtArgs x;
+    // double distribution (model 1): f and g, quasi-equilibrium collision
+    int model;
+    double cv;                // C_v = R/(gamma - 1)
+    double prandtl;           // Pr = tau1/tau2 (<= 1)
+    double thr_qe[2];         // thresholds of the quasi-equilibrium sensor
 };
 
 // D2Q9 passes: the fused step and the three passes of the unfused baseline
@@ -71,8 +76,8 @@ hipError_t launch_d2q9(int dtype, int pass, const D2Q9Args& a, const void* fin, 
 hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fout, void* sens,
                         uint8_t* flags, double* partials, unsigned long long* faults,
                         hipStream_t s);
-// workgroup tile (cells) of the D2Q25 kernel for a storage type
-void d2q25_tile_shape(int dtype, int* tx, int* ty);
+// workgroup tile (cells) of the D2Q25 kernel for a storage type and model
+void d2q25_tile_shape(int dtype, int model, int* tx, int* ty);
 
 // equilibrium initial states from FP64 fields [ny][nx] (n = nx*ny cells)
 hipError_t launch_d2q9_init(int dtype, long long n, double rho0, const double* rho,
@@ -86,6 +91,13 @@ hipError_t launch_d2q9_moments(int dtype, long long n, double rho0, const void* 
                                double* ux, double* uy, double* T, hipStream_t s);
 hipError_t launch_d2q25_moments(int dtype, long long n, double rho0, const void* pop,
                                 double* rho, double* ux, double* uy, double* T, hipStream_t s);
+// double distribution: pop holds [50][n] (f deviations, then g deviations
+// from (C_v - 1) w_i rho0)
+hipError_t launch_d2q25_ddf_init(int dtype, long long n, double rho0, double cv, const double* rho,
+                                 const double* ux, const double* uy, const double* T, void* pop,
+                                 hipStream_t s);
+hipError_t launch_d2q25_ddf_moments(int dtype, long long n, double rho0, double cv, const void* pop,
+                                    double* rho, double* ux, double* uy, double* T, hipStream_t s);
 
 // Reduce partials[step][nblocks][8] of nsteps steps into sums rows
 // (row0 + step) mod max_rows; adds the reference mass/energy n_cells*rho0*(1, e_ref).

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "liblks.so")
 D2Q9, D2Q25 = 9, 25
 F64, F32, BF16, F16 = 0, 1, 2, 3
 PERIODIC, OUTFLOW = 0, 1
-S_KL, S_NEQ, S_PI, S_Q = 1, 2, 4, 8
+S_KL, S_NEQ, S_PI, S_Q, S_QE = 1, 2, 4, 8, 16
+MODEL_BGK, MODEL_DDF = 0, 1
+MODELS = {"bgk": MODEL_BGK, "ddf": MODEL_DDF}
 NSUMS = 8
 # extension sensors (bit k of ext_mask; flag_mask bit 8 + k), plane order
 EXT_NAMES = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf", "comp", "strain")
@@ -61,7 +63,10 @@ class Config(ctypes.Structure):
                 ("flag_mask", ctypes.c_uint32), ("launch_rows", ctypes.c_int32),
                 ("thr", (ctypes.c_double * 2) * 4), ("max_steps", ctypes.c_int32),
                 ("launch_vec", ctypes.c_int32), ("ext_mask", ctypes.c_uint32),
-                ("ext_reserved", ctypes.c_int32), ("thr_ext", (ctypes.c_double * 2) * MAX_EXT)]
+                ("ext_reserved", ctypes.c_int32), ("thr_ext", (ctypes.c_double * 2) * MAX_EXT),
+                ("model", ctypes.c_int32), ("model_reserved", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("thr_qe", ctypes.c_double * 2)]
 
 
 class Box(ctypes.Structure):
@@ -129,7 +134,8 @@ def _stream_handle(device):
 
 def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                 bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
-                launch_rows=0, launch_vec=0, ext=None, thr_ext=None):
+                launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
+                prandtl=0.71, thr_qe=None):
     c = Config()
     c.lattice, c.nx, c.ny = lattice, nx, ny
     c.dtype = DTYPES[dtype] if isinstance(dtype, str) else dtype
@@ -148,6 +154,11 @@ def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, 
           else np.asarray(thr_ext, np.float64).reshape(MAX_EXT, 2))
     for k in range(MAX_EXT):
         c.thr_ext[k][0], c.thr_ext[k][1] = float(te[k, 0]), float(te[k, 1])
+    c.model = MODELS[model] if isinstance(model, str) else model
+    c.model_reserved = 0
+    c.gamma, c.prandtl = gamma, prandtl
+    tq = (math.inf, math.inf) if thr_qe is None else tuple(float(v) for v in thr_qe)
+    c.thr_qe[0], c.thr_qe[1] = tq
     return c
 
 
@@ -170,15 +181,22 @@ class Lattice:
     ext: extension sensors (names from EXT_NAMES, indices or a bit mask);
     thr_ext: [MAX_EXT, 2] thresholds, used for sensors whose flag_x bit is in
     flag_mask.
+    model: "bgk" (default) or, on D2Q25, "ddf" -- the (f, g) double
+    distribution with the quasi-equilibrium collision (gamma, prandtl; pop
+    then holds 50 planes, f then g, and sensors 5 planes, the fifth S_QE with
+    thresholds thr_qe and flag bit S_QE).
     """
 
     def __init__(self, lattice=D2Q9, nx=64, ny=64, dtype="f32", tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                  bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
-                 launch_rows=0, launch_vec=0, ext=None, thr_ext=None, device="cuda"):
+                 launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
+                 prandtl=0.71, thr_qe=None, device="cuda"):
         self.device = torch.device(device)
         self.cfg = make_config(lattice, nx, ny, dtype, tau, mu, dt, dx, bc, rho0, thr, flag_mask,
-                               max_steps, launch_rows, launch_vec, ext, thr_ext)
-        self.Q = lattice
+                               max_steps, launch_rows, launch_vec, ext, thr_ext, model, gamma,
+                               prandtl, thr_qe)
+        self.model = self.cfg.model
+        self.Q = 50 if self.model == MODEL_DDF else lattice
         self.nx, self.ny = nx, ny
         self.dtype = self.cfg.dtype
         nsens = int(lib().lks_sensor_planes(ctypes.byref(self.cfg))) or \
@@ -187,7 +205,7 @@ class Lattice:
         sdt = torch.float64 if self.dtype == F64 else torch.float32
         tdt = _TORCH_STORE[self.dtype]
         dev = self.device
-        self.pop = [torch.zeros((lattice, ny, nx), dtype=tdt, device=dev) for _ in range(2)]
+        self.pop = [torch.zeros((self.Q, ny, nx), dtype=tdt, device=dev) for _ in range(2)]
         self.sensors = torch.zeros((nsens, ny, nx), dtype=sdt, device=dev)
         self.flags = torch.zeros((ny, nx), dtype=torch.uint8, device=dev)
         self.sums = torch.zeros((max_steps, NSUMS), dtype=torch.float64, device=dev)
@@ -228,7 +246,7 @@ class Lattice:
         k = EXT_NAMES.index(name)
         if not self.ext_mask & (1 << k):
             raise KeyError(name)
-        base = int(lib().lks_num_sensors(self.Q))
+        base = int(lib().lks_num_sensors(self.cfg.lattice))
         return self.sensors[base + bin(self.ext_mask & ((1 << k) - 1)).count("1")]
 
     def __del__(self):

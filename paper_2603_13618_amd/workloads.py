@@ -1,6 +1,6 @@
 """Named workloads: grid, lattice, parameters and frozen refinement thresholds.
 
-Thresholds (theta1, theta2) per sensor (S_KL, S_NEQ, S_PI[, S_Q]) are frozen
+Thresholds (theta1, theta2) per sensor (S_KL, S_NEQ, S_PI[, S_Q][, S_QE]) are frozen
 from the FP64 reference run at the workload's final step, rounded to two
 significant digits (the paper gives its thresholds only inside its figures):
 the 90th and 99th percentiles over all cells for the smooth fields, 1 % and
@@ -36,6 +36,16 @@ RIEMANN_2048 = dict(
     lattice=25, nx=2048, ny=2048, mu=1e-3, cfl=0.01, steps=200, seed=0,
     flag_mask=1 | 2 | 4 | 8,
     thr=[[4e-05, 0.0004], [0.00068, 0.0068], [0.001, 0.01], [0.00058, 0.0058]],
+)
+
+RIEMANN_2048_DDF = dict(
+    name="four-quadrant Riemann problem, D2Q25 FV double distribution (f, g) with the "
+         "quasi-equilibrium collision, air (gamma=1.4, Pr=0.71), 2048x2048 outflow, mu=1e-3, "
+         "200 steps",
+    lattice=25, nx=2048, ny=2048, mu=1e-3, cfl=0.01, steps=200, seed=0, gamma=1.4, prandtl=0.71,
+    flag_mask=1 | 2 | 4 | 8 | 16,
+    thr=[[0.00041, 0.0041], [0.0022, 0.022], [0.0011, 0.011], [0.0011, 0.011]],
+    thr_qe=[0.0006, 0.006],
 )
 
 ADJOINT_1024 = dict(

@@ -48,7 +48,7 @@ def flags_outside_band(gpu_flags, ref_flags, ref_sens, thr, mask, tol):
     tol * max|s| from every enabled threshold.  Returns (n_mismatch, n_excluded)."""
     gpu_flags, ref_flags = to_f64(gpu_flags), to_f64(ref_flags)
     near = np.zeros(ref_flags.shape, bool)
-    for k in range(4):
+    for k in range(len(thr)):
         if mask & (1 << k):
             s = ref_sens[k]
             band = tol[k] * np.abs(s[np.isfinite(s)]).max() if np.isfinite(s).any() else 0

@@ -57,7 +57,8 @@ def test_abi_struct_layout_matches_header(tmp_path):
     # sizes and offsets of the ctypes mirror against what the C compiler makes
     # of include/lks.h
     fields = ["lattice", "nx", "dtype", "tau", "rho0", "flag_mask", "launch_rows", "thr",
-              "max_steps", "launch_vec", "ext_mask", "ext_reserved", "thr_ext"]
+              "max_steps", "launch_vec", "ext_mask", "ext_reserved", "thr_ext", "model",
+              "model_reserved", "gamma", "prandtl", "thr_qe"]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lks.h\"\nint main(void){\n"
                    + 'printf("%zu %zu", sizeof(lks_config), sizeof(lks_buffers));\n'
@@ -93,6 +94,29 @@ def test_extension_sensor_validation_on_host():
         assert lks.scratch_bytes(c) == 0 and L.lks_sensor_planes(ctypes.byref(c)) == 0
     r = lks.make_config(9, 64, 64, "f32", tau=0.6)
     r.ext_reserved = 1
+    assert lks.scratch_bytes(r) == 0
+
+
+def test_double_distribution_validation_on_host():
+    L = lks.lib()
+    kw = dict(mu=1e-3, dt=1e-3, dx=0.1, model="ddf", gamma=1.4, prandtl=0.71)
+    ok = lks.make_config(25, 64, 64, "f32", flag_mask=31, thr_qe=(1e-4, 1e-3), **kw)
+    assert lks.scratch_bytes(ok) > 0 and L.lks_sensor_planes(ctypes.byref(ok)) == 5
+    # the QE flag bit belongs to the double distribution only
+    bgk = lks.make_config(25, 64, 64, "f32", mu=1e-3, dt=1e-3, dx=0.1, flag_mask=16)
+    assert lks.scratch_bytes(bgk) == 0
+    bad = [lks.make_config(9, 64, 64, "f32", tau=0.6, model="ddf"),          # D2Q25 only
+           lks.make_config(25, 64, 64, "f32", **dict(kw, gamma=2.0)),       # C_v - 1 = 0
+           lks.make_config(25, 64, 64, "f32", **dict(kw, gamma=1.0)),
+           lks.make_config(25, 64, 64, "f32", **dict(kw, prandtl=1.5)),     # Pr <= 1
+           lks.make_config(25, 64, 64, "f32", **dict(kw, prandtl=0.0)),
+           lks.make_config(25, 64, 64, "f32", thr_qe=(2.0, 1.0), **kw),
+           lks.make_config(25, 64, 64, "f32", flag_mask=32, **kw),
+           lks.make_config(25, 64, 64, "f32", mu=1e-3, dt=1e-3, dx=0.1, model=2)]
+    for c in bad:
+        assert lks.scratch_bytes(c) == 0 and L.lks_sensor_planes(ctypes.byref(c)) == 0
+    r = lks.make_config(25, 64, 64, "f32", **kw)
+    r.model_reserved = 1
     assert lks.scratch_bytes(r) == 0
 
 

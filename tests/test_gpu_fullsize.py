@@ -136,6 +136,48 @@ def test_riemann_2048_fp32_200_steps(orc):
         assert bad == 0, (bad, excl)
 
 
+def test_riemann_2048_ddf_fp32_sampled(orc):
+    # the double-distribution workload in the benchmark's launch configuration;
+    # 60 steps keep the oracle windows (radius 2 cells per step) small
+    wl = workloads.RIEMANN_2048_DDF
+    n, mu, gamma, pr = wl["nx"], wl["mu"], wl["gamma"], wl["prandtl"]
+    steps = 60
+    thr, mask = np.asarray(wl["thr"]), wl["flag_mask"]
+    thr5 = np.vstack([thr, [wl["thr_qe"]]])
+    rho, ux, uy, T, states = inputs.riemann_quadrants(n, seed=0)
+    dx = 1.0 / n
+    dt = inputs.riemann_dt(states, dx, gamma=gamma)
+    lat = lks.Lattice(25, n, n, "f32", mu=mu, dt=dt, dx=dx, bc=(1, 1), thr=thr, flag_mask=mask,
+                      max_steps=steps, model="ddf", gamma=gamma, prandtl=pr, thr_qe=wl["thr_qe"])
+    lat.init(rho, ux, uy, T)
+    lat.step(steps)
+    torch.cuda.synchronize()
+    assert lat.check() == 0
+    for (x0, y0) in ((n // 2 - P // 2, n // 2 - P // 2), (0, n // 2 - 3)):
+        R = 2 * steps + 2
+        wx0, wy0 = max(x0 - R, 0), max(y0 - R, 0)
+        wx1, wy1 = min(x0 + P + R, n), min(y0 + P + R, n)
+        f = inputs.riemann_quadrants(n, seed=0, window=(wx0, wy0, wx1 - wx0, wy1 - wy0))
+        out = orc.ddf_run(orc.ddf_equilibrium(*f[:4], gamma), steps, mu, dt, dx, bc=(1, 1),
+                          gamma=gamma, prandtl=pr, thr=thr5, mask=mask)
+        sl = (slice(y0 - wy0, y0 - wy0 + P), slice(x0 - wx0, x0 - wx0 + P))
+        m = orc.ddf_moments(out["f"], gamma)[(slice(None),) + sl]
+        r, u, v, t = (_patch(a, y0, x0) for a in lat.moments())
+        e_rho = np.abs(r - m[0]).max()
+        e_u = np.hypot(u - m[1], v - m[2]).max() / np.hypot(m[1], m[2]).max()
+        e_T = np.abs(t - m[3]).max() / m[3].max()
+        sens = out["sens"][(slice(None),) + sl]
+        es = [np.abs(_patch(lat.sensors[k], y0, x0) - sens[k]).max() / max(np.abs(sens[k]).max(), 1e-30)
+              for k in range(5)]
+        print(f"patch ({x0},{y0}): rho {e_rho:.2e} u {e_u:.2e} T {e_T:.2e} sensors "
+              + " ".join(f"{e:.2e}" for e in es), flush=True)
+        assert e_rho <= 1e-5 and e_u <= 1e-5 and e_T <= 1e-5
+        assert max(es) <= 1e-3
+        bad, excl = flags_outside_band(_patch(lat.flags, y0, x0), out["flags"][sl], sens, thr5,
+                                       mask, [max(e, 1e-6) for e in es])
+        assert bad == 0, (bad, excl)
+
+
 def test_adjoint_1024_200_steps_sampled_gradient(orc):
     """Gradient of the summed KL sensor on the 1024^2 differentiation workload
     (FP32, checkpoint 20) at sampled cells, against central differences of the

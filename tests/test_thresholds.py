@@ -16,6 +16,10 @@ def test_package_thresholds_match_golden():
                     ("C3", workloads.RIEMANN_2048)):
         rows = np.asarray(data[key])
         np.testing.assert_array_equal(np.asarray(wl["thr"])[: rows.shape[0]], rows)
+    # the double distribution: four base rows, then the quasi-equilibrium sensor
+    rows = np.asarray(data["C4"])
+    wl = workloads.RIEMANN_2048_DDF
+    np.testing.assert_array_equal(np.vstack([wl["thr"], [wl["thr_qe"]]]), rows)
 
 
 def test_c1_thresholds_reproduce():

@@ -36,7 +36,7 @@ FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 # the double-distribution step (FP32): 50 x 4 read + 50 x 4 written + 5 x 4
 # sensors + 1 flag per cell
 BYTES_F32_DDF = 421
-DDF_KERNEL = "d2q25_ddf_kernel<float,32,4>"
+DDF_KERNEL = "d2q25_ddf_kernel<float,16,8>"
 
 
 def parse():

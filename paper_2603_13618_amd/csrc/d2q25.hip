@@ -28,31 +28,29 @@
 #include "lks_device.h"
 #include "lks_internal.h"
 
-// Double distribution: 1 = stage f, then g, through one 25-plane LDS buffer
-// (own-cell values held in registers); 0 = stage all 50 planes at once.
-#ifndef LKS_DDF_SEQ
-#define LKS_DDF_SEQ 1
-#endif
-// its FP32 workgroup tile (cells) and minimum waves per SIMD (0 = compiler)
+// FP32 workgroup tile (cells) of the double-distribution kernel and the
+// minimum waves per SIMD its register allocation must allow (0 = compiler's
+// choice).  Measured at 2048^2: left alone the compiler takes ~300 registers
+// (one wave per SIMD); forcing two waves spills ~60 of them to scratch (cache
+// resident) and is 1.2x faster; three spill far more and are 2x slower.
+// Narrow tiles let more workgroups share a CU across the barriers and 16 x 8
+// stages the fewest halo cells per cell of the shapes that fit.
 #ifndef LKS_DDF_TX
-#define LKS_DDF_TX 32
+#define LKS_DDF_TX 16
 #endif
 #ifndef LKS_DDF_TY
-#define LKS_DDF_TY 4
+#define LKS_DDF_TY 8
 #endif
 #ifndef LKS_DDF_WAVES
-#define LKS_DDF_WAVES 0
+#define LKS_DDF_WAVES 2
+#endif
+#if LKS_DDF_WAVES > 0
+#define LKS_DDF_ATTR __attribute__((amdgpu_waves_per_eu(LKS_DDF_WAVES)))
+#else
+#define LKS_DDF_ATTR
 #endif
 
 namespace lks {
-
-// an opaque copy that is neither merged with another nor moved across other
-// side effects (volatile asm): forces a recomputation at this point
-template <typename T> __device__ __forceinline__ T fresh(T v)
-{
-    asm volatile("" : "+v"(v));
-    return v;
-}
 
 // GH5 nodes (x-node a, y-node b), He_n(xi)/n! and 1D weights, T_ref = 1
 __device__ __forceinline__ constexpr double gh5_xi(int a)
@@ -432,265 +430,18 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
 // sensor-TauNS-kin, sensor-qNSF-kin-ryk, Sensor-qe-kin).
 // Storage: [50][ny][nx], f deviations from w rho0, then g deviations from
 // (C_v - 1) w rho0.
+//
+// f and g are staged one after the other through one 25-plane LDS buffer
+// (the tile and its two-cell cross halo, as in d2q25_kernel): the own-cell g
+// values stay in registers from the start (the moments need them).  Pass 1
+// over the velocities takes the non-equilibrium parts of both: the sensors
+// and the heat fluxes q_f = 1/2 sum |c|^2 c f^neq, q_g = sum c g^neq (c = v - u;
+// the equilibria carry none, so no cancellation), and keeps the 25
+// equilibrium deviations for pass 2.  Pass 2 applies the collision and the
+// fluxes to f; g is then staged into the same buffer and updated.
 // ---------------------------------------------------------------------------
 template <typename S, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void d2q25_ddf_kernel(D2Q25Args a,
-                                                       const typename Store<S>::raw* __restrict__ fin,
-                                                       typename Store<S>::raw* __restrict__ fout,
-                                                       typename Store<S>::real* __restrict__ sens,
-                                                       uint8_t* __restrict__ flags,
-                                                       double* __restrict__ partials,
-                                                       unsigned long long* __restrict__ faults)
-{
-    using R = typename Store<S>::real;
-    using T = Tile<TX, TY>;
-    constexpr int NT = TX * TY;
-    __shared__ R lds[50 * T::kPlane];
-
-    const int nx = a.nx, ny = a.ny;
-    const long long plane = a.plane;
-    int tile_x, tile_y;
-    {
-        const int b = blockIdx.x;
-        if (a.tiles_x % 8 == 0) {
-            const int bw = a.tiles_x / 8, l = b / 8;
-            tile_x = (b % 8) * bw + l % bw;
-            tile_y = l / bw;
-        } else {
-            tile_x = b % a.tiles_x;
-            tile_y = b / a.tiles_x;
-        }
-    }
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int X0 = tile_x * TX, Y0 = tile_y * TY;
-    const int X = X0 + tx, Y = Y0 + ty;
-    const bool active = X < nx && Y < ny;
-    const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
-
-    constexpr int HR = (4 * TX + NT - 1) / NT;
-    long long own = (long long)gyc * nx + gxc;
-    long long hoff[HR];
-    int hlds[HR];
-#pragma unroll
-    for (int k = 0; k < HR; ++k) {
-        const int h = threadIdx.x + k * NT;
-        const int hr = h / TX, c = h % TX;
-        const int r = hr < 2 ? hr - 2 : TY + hr - 2;
-        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
-        hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
-    }
-    long long coff = 0;
-    int clds = -1;
-    if (threadIdx.x < 4 * TY) {
-        const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
-        const int c = hc < 2 ? hc - 2 : TX + hc - 2;
-        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
-        clds = T::rowbase(r) + c;
-    }
-    const int olds = T::rowbase(ty) + tx;
-
-    // ---- stage the 50 planes (f, then g) and accumulate the moments the
-    //      equilibria need: sum d, sum v d, sum |v|^2 d of f and sum dg of g
-    const R rho0 = R(a.rho0);
-    const R cv = R(a.cv);
-    R drho = R(0), jx = R(0), jy = R(0), m2 = R(0), dg0 = R(0);
-    // one distribution at a time keeps only 25 planes' loads in flight
-#pragma nounroll
-    for (int dist = 0; dist < 2; ++dist) {
-        R vin[25], vh[HR][25], vc[25];
-        sfor25<25>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const typename Store<S>::raw* src = fin + (25 * dist + i) * plane;
-            vin[i] = Store<S>::to_real(src[own]);
-#pragma unroll
-            for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
-            vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
-        });
-        sfor25<25>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int ia = i / 5, ib = i % 5;
-            R* dst = lds + (25 * dist + i) * T::kPlane;
-            const R v = vin[i];
-            dst[olds] = v;
-#pragma unroll
-            for (int k = 0; k < HR; ++k)
-                if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];
-            if (clds >= 0) dst[clds] = vc[i];
-            if (dist == 0) {
-                drho += v;
-                if (ia != 2) jx += R(gh5_xi(ia)) * v;
-                if (ib != 2) jy += R(gh5_xi(ib)) * v;
-                m2 += R(gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) * v;
-            } else {
-                dg0 += v;
-            }
-        });
-    }
-    __syncthreads();
-
-    // ---- cell state
-    const R rho = rho0 + drho;
-    const R irho = R(1) / rho;
-    const R ux = jx * irho, uy = jy * irho;
-    // C_v (T - 1) = (E - C_v rho)/rho - |u|^2/2 with E - C_v rho = dg0 + m2/2
-    // - C_v drho (sum_i w_i = 1, sum_i w_i |v_i|^2/2 = 1: the reference parts cancel)
-    const R tm1 = ((dg0 + R(0.5) * m2 - cv * drho) * irho - R(0.5) * (ux * ux + uy * uy)) / cv;
-    const R Tc = R(1) + tm1;
-    const R gfac = cv - R(1);                              // g^eq = (C_v - 1) T f^eq
-    const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
-                       T::rowbase(ty + 2)};
-    const int own_lds = rb[2] + tx;
-
-    // ---- pass 1: non-equilibrium parts of f and g: the sensors and the heat
-    //      fluxes q_f = 1/2 sum |c|^2 c f^neq, q_g = sum c g^neq (c = v - u; the
-    //      equilibria carry none, so the non-equilibrium parts give them
-    //      without cancellation)
-    R klf = R(0), klg = R(0), gsum = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0),
-      qy = R(0), qfx = R(0), qfy = R(0), qgx = R(0), qgy = R(0);
-    // positivity (f, f^eq, g, g^eq > 0) and the reach of the KL series,
-    // tested per population (lane masks, no values kept for later)
-    bool nonpos = false, far = false;
-    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
-        const int i = 5 * ia + ib;
-        const R w = R(gh5_w(ia) * gh5_w(ib));
-        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
-        const R d = lds[i * T::kPlane + own_lds], dg = lds[(25 + i) * T::kPlane + own_lds];
-        const R fneq = d - deq;
-        const R feq = w * rho0 + deq;
-        const R x = fneq * rcp(feq);
-        // deviation of g^eq from (C_v - 1) w rho0: (C_v - 1)(T deq + (T - 1) w rho0)
-        const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
-        const R gneq = dg - dgeq;
-        const R geq = gfac * (w * rho0) + dgeq;
-        const R y = gneq * rcp(geq);
-        klf += (fneq * x) * kl_series(x);
-        klg += (gneq * y) * kl_series(y);
-        gsum += gneq;
-        nonpos |= !(feq > R(0)) | !(geq > R(0)) | !(x > R(-1)) | !(y > R(-1));
-        far |= !(fabs(x) <= KlCut<R>::v) | !(fabs(y) <= KlCut<R>::v);
-        neq += fabs(fneq) + fabs(gneq);
-        pxx += vx * vx * fneq;
-        pxy += vx * vy * fneq;
-        pyy += vy * vy * fneq;
-        const R e = R(0.5) * (vx * vx + vy * vy);
-        qx += vx * (gneq + e * fneq);
-        qy += vy * (gneq + e * fneq);
-        const R cx = vx - ux, cy = vy - uy;
-        const R hc = R(0.5) * (cx * cx + cy * cy) * fneq;
-        qfx += hc * cx;
-        qfy += hc * cy;
-        qgx += cx * gneq;
-        qgy += cy * gneq;
-    });
-    if (far) {
-        // rare: some population far from equilibrium (or NaN): the closed form
-        klf = R(0);
-        klg = R(0);
-        d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
-            const int i = 5 * ia + ib;
-            const R w = R(gh5_w(ia) * gh5_w(ib));
-            const R d = lds[i * T::kPlane + own_lds], dg = lds[(25 + i) * T::kPlane + own_lds];
-            const R feq = w * rho0 + deq;
-            const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
-            const R geq = gfac * (w * rho0) + dgeq;
-            klf += feq * kl_phi((d - deq) * rcp(feq));
-            klg += geq * kl_phi((dg - dgeq) * rcp(geq));
-            // one population at a time: the rare path must not set the
-            // kernel's register budget
-            __builtin_amdgcn_sched_barrier(0);
-        });
-    }
-
-    // ---- pass 2: quasi-equilibrium collision and van Leer fluxes.
-    //      f' = f - A div - (dt/tau1)(f - f^eq) + (dt/tau1 - dt/tau2)(f* - f^eq)
-    const R A = R(a.dt / a.dx);
-    const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
-    const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
-    const long long off = (long long)Y * nx + X;
-    R qe = R(0);
-    auto div_of = [&](const R* t, R d, int ia, int ib, R vx, R vy) {
-        R div = R(0);
-        if (ia != 2) {
-            const R* row = t + own_lds;
-            div += vx * (ia > 2 ? flux_diff<R, 1>(row[-2], row[-1], d, row[1], R(0))
-                                : flux_diff<R, -1>(R(0), row[-1], d, row[1], row[2]));
-        }
-        if (ib != 2) {
-            div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
-                                : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
-        }
-        return div;
-    };
-    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
-        const int i = 5 * ia + ib;
-        const R w = R(gh5_w(ia) * gh5_w(ib));
-        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
-        const R* tf = lds + i * T::kPlane;
-        const R* tg = lds + (25 + i) * T::kPlane;
-        const R d = tf[own_lds], dg = tg[own_lds];
-        const R fneq = d - deq;
-        const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
-        // f* - f^eq = w (q_f . v)(|v|^2/4 - 1), g* - g^eq = w (q_g . v)
-        const R dfs = w * (qfx * vx + qfy * vy) * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
-        const R dgs = w * (qgx * vx + qgy * vy);
-        qe += fabs(dfs) + fabs(dgs);
-        const R divf = div_of(tf, d, ia, ib, vx, vy);
-        const R divg = div_of(tg, dg, ia, ib, vx, vy);
-        if (active) {
-            fout[i * plane + off] = Store<S>::from_real(d - A * divf - B1 * fneq + B12 * dfs);
-            fout[(25 + i) * plane + off] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
-        }
-    });
-    // sum f ln(f/f^eq) = sum f^eq phi(x) (f and f^eq carry the same mass);
-    // sum g ln(g/g^eq) = sum g^eq phi(y) + sum g^neq
-    const R klsum = fabs(klf) + fabs(klg + gsum);
-    const bool fault = nonpos || !(klsum == klsum);
-    const R s_kl = fault ? R(INFINITY) : klsum;
-    const R s_pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
-    const R s_q = sqrt(qx * qx + qy * qy);
-    double acc[kNsums];
-#pragma unroll
-    for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
-    if (active) {
-        const R sv[5] = {s_kl, neq, s_pi, s_q, qe};
-        int level = 0;
-#pragma unroll
-        for (int s = 0; s < 5; ++s) {
-            if (a.mask & (1u << s)) {
-                const R t0 = s < 4 ? R(a.thr[s][0]) : R(a.thr_qe[0]);
-                const R t1 = s < 4 ? R(a.thr[s][1]) : R(a.thr_qe[1]);
-                const int l = (sv[s] > t0) + (sv[s] > t1);
-                level = l > level ? l : level;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < 5; ++s) sens[s * plane + off] = sv[s];
-        flags[off] = fault ? uint8_t(0x82) : uint8_t(level);
-        if (fault) atomicAdd(faults, 1ull);
-        acc[0] = (double)drho;
-        acc[1] = (double)jx;
-        acc[2] = (double)jy;
-        acc[3] = (double)dg0 + 0.5 * (double)m2;     // E - C_v rho0
-        acc[4] = (double)s_kl;
-        acc[5] = (double)neq;
-        acc[6] = (double)s_pi;
-        acc[7] = (double)s_q;
-    }
-    block_sums_n<NT / kWave>(acc, partials + (long long)blockIdx.x * kNsums);
-}
-
-// The same step with f and g staged one after the other through a 25-plane
-// LDS buffer (half the LDS of staging both, so more workgroups per CU): the
-// own-cell values of f and g stay in registers; f is staged with its halo,
-// the moments, pass 1 and the f update run, then g is staged into the same
-// buffer and updated.  Same arithmetic as d2q25_ddf_kernel.
-#if LKS_DDF_WAVES > 0
-#define LKS_DDF_ATTR __attribute__((amdgpu_waves_per_eu(LKS_DDF_WAVES)))
-#else
-#define LKS_DDF_ATTR
-#endif
-template <typename S, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_seq_kernel(
+__global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_kernel(
     D2Q25Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ partials,
     unsigned long long* __restrict__ faults)
@@ -743,9 +494,9 @@ __global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_seq_kernel(
     const int olds = T::rowbase(ty) + tx;
     const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
                        T::rowbase(ty + 2)};
-    const int own_lds = rb[2] + tx;
 
     // stage planes [p0, p0 + 25) with their halo; own-cell values into own_v
+    // (loaded here unless own_loaded)
     auto stage = [&](int p0, R (&own_v)[25], bool own_loaded) {
         R vh[HR][25], vc[25];
         sfor25<25>([&](auto ic) {
@@ -792,26 +543,28 @@ __global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_seq_kernel(
     const R rho = rho0 + drho;
     const R irho = R(1) / rho;
     const R ux = jx * irho, uy = jy * irho;
+    // C_v (T - 1) = (E - C_v rho)/rho - |u|^2/2 with E - C_v rho = dg0 + m2/2
+    // - C_v drho (sum_i w_i = 1, sum_i w_i |v_i|^2/2 = 1: the reference parts cancel)
     const R tm1 = ((dg0 + R(0.5) * m2 - cv * drho) * irho - R(0.5) * (ux * ux + uy * uy)) / cv;
     const R Tc = R(1) + tm1;
-    const R gfac = cv - R(1);
+    const R gfac = cv - R(1);                              // g^eq = (C_v - 1) T f^eq
 
-    __syncthreads();
-
-    // ---- pass 1: sensors and the heat fluxes of f and g (as d2q25_ddf_kernel);
-    //      f's own-cell values are read back from the staged buffer
+    // ---- pass 1: non-equilibrium parts of f and g (sensors, heat fluxes)
     R klf = R(0), klg = R(0), gsum = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0),
       qy = R(0), qfx = R(0), qfy = R(0), qgx = R(0), qgy = R(0);
-    // positivity (f, f^eq, g, g^eq > 0) and the reach of the KL series,
-    // tested per population (lane masks, no values kept for later)
+    // positivity (f, f^eq, g, g^eq > 0) and the reach of the KL series, per
+    // population (lane masks)
     bool nonpos = false, far = false;
+    R deqv[25];
     d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
         const int i = 5 * ia + ib;
         const R w = R(gh5_w(ia) * gh5_w(ib));
         const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
-        const R fneq = lds[i * T::kPlane + own_lds] - deq;
+        deqv[i] = deq;
+        const R fneq = fc[i] - deq;
         const R feq = w * rho0 + deq;
         const R x = fneq * rcp(feq);
+        // deviation of g^eq from (C_v - 1) w rho0: (C_v - 1)(T deq + (T - 1) w rho0)
         const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
         const R gneq = gc[i] - dgeq;
         const R geq = gfac * (w * rho0) + dgeq;
@@ -835,31 +588,32 @@ __global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_seq_kernel(
         qgx += cx * gneq;
         qgy += cy * gneq;
     });
-    // Each later pass recomputes the equilibria from opaque copies (fresh) of
-    // the moments: the compiler would otherwise keep pass 1's 25 values live
-    // through the passes instead of recomputing them (same arithmetic).
     if (far) {
+        // rare: some population far from equilibrium (or NaN): the closed
+        // form, one population at a time
         klf = R(0);
         klg = R(0);
-        d2q25_deq<R>(fresh(drho), fresh(rho), fresh(ux), fresh(uy), fresh(tm1), [&](int ia, int ib, R deq) {
-            const int i = 5 * ia + ib;
-            const R w = R(gh5_w(ia) * gh5_w(ib));
+        sfor25<25>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const R w = R(gh5_w(i / 5) * gh5_w(i % 5));
+            const R deq = deqv[i];
             const R feq = w * rho0 + deq;
             const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
             const R geq = gfac * (w * rho0) + dgeq;
-            klf += feq * kl_phi((lds[i * T::kPlane + own_lds] - deq) * rcp(feq));
+            klf += feq * kl_phi((fc[i] - deq) * rcp(feq));
             klg += geq * kl_phi((gc[i] - dgeq) * rcp(geq));
-            // one population at a time: the rare path must not set the
-            // kernel's register budget
             __builtin_amdgcn_sched_barrier(0);
         });
     }
 
-    // ---- pass 2: f, then g (the LDS buffer is reused)
+    // ---- pass 2: f' = f - A div - (dt/tau1)(f - f^eq) + (dt/tau1 - dt/tau2)(f* - f^eq),
+    //      f first, then g through the same buffer
     const R A = R(a.dt / a.dx);
-    const R B1 = R(a.dt) * rho * Tc / R(a.mu);
-    const R B12 = B1 * (R(1) - R(a.prandtl));
+    const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
+    const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
     const long long off = (long long)Y * nx + X;
+    const int own_lds = rb[2] + tx;
+    __syncthreads();              // the staged f of the whole tile (pass 1 read registers only)
     auto div_of = [&](const R* t, R d, int ia, int ib, R vx, R vy) {
         R div = R(0);
         if (ia != 2) {
@@ -874,12 +628,14 @@ __global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_seq_kernel(
         return div;
     };
     R qe = R(0);
-    d2q25_deq<R>(fresh(drho), fresh(rho), fresh(ux), fresh(uy), fresh(tm1), [&](int ia, int ib, R deq) {
-        const int i = 5 * ia + ib;
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ia = i / 5, ib = i % 5;
         const R w = R(gh5_w(ia) * gh5_w(ib));
         const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
-        const R d = lds[i * T::kPlane + own_lds];
-        const R fneq = d - deq;
+        const R d = fc[i];
+        const R fneq = d - deqv[i];
+        // f* - f^eq = w (q_f . v)(|v|^2/4 - 1)
         const R dfs = w * (qfx * vx + qfy * vy) * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
         qe += fabs(dfs);
         const R divf = div_of(lds + i * T::kPlane, d, ia, ib, vx, vy);
@@ -888,18 +644,22 @@ __global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_seq_kernel(
     __syncthreads();              // every f read of the buffer is done
     stage(25, gc, true);
     __syncthreads();
-    d2q25_deq<R>(fresh(drho), fresh(rho), fresh(ux), fresh(uy), fresh(tm1), [&](int ia, int ib, R deq) {
-        const int i = 5 * ia + ib;
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ia = i / 5, ib = i % 5;
         const R w = R(gh5_w(ia) * gh5_w(ib));
         const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
         const R dg = gc[i];
-        const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
+        const R gneq = dg - gfac * (Tc * deqv[i] + tm1 * (w * rho0));
+        // g* - g^eq = w (q_g . v)
         const R dgs = w * (qgx * vx + qgy * vy);
         qe += fabs(dgs);
         const R divg = div_of(lds + i * T::kPlane, dg, ia, ib, vx, vy);
         if (active) fout[(25 + i) * plane + off] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
     });
 
+    // sum f ln(f/f^eq) = sum f^eq phi(x) (f and f^eq carry the same mass);
+    // sum g ln(g/g^eq) = sum g^eq phi(y) + sum g^neq
     const R klsum = fabs(klf) + fabs(klg + gsum);
     const bool fault = nonpos || !(klsum == klsum);
     const R s_kl = fault ? R(INFINITY) : klsum;
@@ -944,12 +704,8 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
     using raw = typename Store<S>::raw;
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
-    if (LKS_DDF_SEQ)
-        d2q25_ddf_seq_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
-            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
-    else
-        d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
-            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+        a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     return hipGetLastError();
 }
 

@@ -127,6 +127,52 @@ def riemann_dt(states, dx, cfl=0.01, gamma=2.0):
     return cfl * dx / smax
 
 
+# The paper's own workloads (Sec. IV): analytic initial conditions, air
+# (gamma = 1.4, R = 1, T = p / rho), equilibrium populations.
+
+SOD_STATES = ((1.0, 1.0, 0.0), (0.125, 0.1, 0.0))      # (rho, p, u_x) left / right of x = 1/2
+
+
+def sod_tube(nx, ny=2):
+    """Sod shock tube on x in [0, 1] (cell-centred, split at 1/2), run as
+    pseudo-1D on an nx x ny grid (periodic in y).  Returns rho, ux, uy, T."""
+    x = (np.arange(nx) + 0.5) / nx
+    left = x <= 0.5
+    (rl, pl, ul), (rr, pr, ur) = SOD_STATES
+    rho = np.where(left, rl, rr)
+    p = np.where(left, pl, pr)
+    u = np.where(left, ul, ur)
+    one = np.ones((ny, 1))
+    return rho * one, u * one, 0.0 * rho * one, (p / rho) * one
+
+
+# modified configuration 3 of the 2D Riemann problems: quadrants split at
+# x = y = 0.85; (rho, p, u_x, u_y) for NE, NW, SW, SE
+CASE3_STATES = ((1.5, 1.5, 0.0, 0.0), (0.5323, 0.3, 1.206, 0.0), (0.138, 0.029, 1.206, 1.206),
+                (0.5323, 0.3, 0.0, 1.206))
+
+
+def riemann_case3(n, window=None):
+    """The modified 2D Riemann problem No. 3 on [0, 1]^2 (cell-centred, split
+    at 0.85).  window = (x0, y0, wx, wy) selects a sub-block.  Returns rho,
+    ux, uy, T."""
+    x0, y0, wx, wy = (0, 0, n, n) if window is None else window
+    x = (np.arange(x0, x0 + wx) + 0.5) / n
+    y = (np.arange(y0, y0 + wy) + 0.5) / n
+    X, Y = np.meshgrid(x, y)
+    east, north = X >= 0.85, Y >= 0.85
+    quad = np.where(north & east, 0, np.where(north, 1, np.where(~east, 2, 3)))
+    rho, p, ux, uy = (np.choose(quad, [s[k] for s in CASE3_STATES]).astype(np.float64) for k in range(4))
+    return rho, ux, uy, p / rho
+
+
+def cfl_dt(fields, dx, gamma=1.4, cfl=0.01):
+    """The paper's time step rule dt = CFL min(dx, dy) / max(|u| + c_s), c_s =
+    sqrt(gamma T), from the initial fields (rho, ux, uy, T)."""
+    _, ux, uy, T = fields
+    return cfl * dx / float(np.max(np.hypot(ux, uy) + np.sqrt(gamma * T)))
+
+
 def shear_wave(n, amp=1e-4, ny=None):
     """rho = 1, ux = amp sin(2 pi y / ny), uy = 0 on an n x ny grid."""
     ny = n if ny is None else ny

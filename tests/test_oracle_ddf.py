@@ -196,3 +196,25 @@ def test_sensors_of_a_quasi_equilibrium_state(orc):
     qg = [(c * x[25:]).sum(0) for c in (vx, vy)]
     assert np.allclose(s[3], np.hypot(qf[0] + qg[0], qf[1] + qg[1]), rtol=1e-12, atol=0)
     assert (s[0] > 0).all()
+
+
+def test_grad_hermite_equilibria_of_the_paper_cases(orc):
+    # On the 25-velocity set the order-4 Grad-Hermite equilibrium is not
+    # positive everywhere: Sod's star region (u* = 0.927, T = 0.711) dips to
+    # about -3e-4 rho, and three of the four states of the 2D Riemann case 3
+    # to -8 % of rho, whatever the lattice temperature (a change of T_ref is
+    # a rescaling u -> u/sqrt(T_ref), T -> T/T_ref of the same problem).
+    from oracle import riemann_exact as rx
+    xi = np.linspace(-2, 2, 2001)
+    r, u, p = rx.sample(*inputs.SOD_STATES, xi, GAMMA)
+    f = orc.ddf_equilibrium(r[None, :], u[None, :], 0 * u[None, :], (p / r)[None, :], GAMMA)
+    m = (f[:25] / r).min()
+    assert -5e-4 < m < -1e-4
+    assert (f[:, 0, np.abs(xi + 1.5) < 0.1] > 0).all()      # the undisturbed left state
+    st = np.array(inputs.CASE3_STATES)
+    for Tr in (0.5, 1.0, 2.0, 4.0):
+        s = np.sqrt(Tr)
+        f = orc.ddf_equilibrium(st[None, :, 0], st[None, :, 2] / s, st[None, :, 3] / s,
+                                (st[:, 1] / st[:, 0])[None, :] / Tr, GAMMA)
+        neg = (f <= 0).any(axis=0)[0]
+        assert neg.sum() >= 3 and (f[:25] / st[:, 0]).min() < -0.05

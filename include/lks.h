@@ -266,6 +266,41 @@ const char* lks_status_str(lks_status s);
  * when ctx is NULL); valid until the next call on the same context. */
 const char* lks_last_error(const lks_ctx* ctx);
 
+/* ---- Macroscopic class-1 sensors (central differences) ----
+ * The macroscopic counterparts of the class-1 sensors (Sec. III.A, eqs.
+ * sensor-TauNS-mac, sensor-C-mac, sensor-S-mac, the rate-of-strain and
+ * heat-flux forms), which the paper computes with central finite differences
+ * to compare the kinetic sensors with (Sec. IV).  With A_ab = d_a u_b and
+ * D = 2:
+ *   LKS_M_TAU   |tau_NS|_F, tau_NS = -mu (A + A^T) - lambda (div u) I
+ *   LKS_M_C     sqrt(D) |div u|
+ *   LKS_M_S     |A + A^T - (2/D)(div u) I|_F
+ *   LKS_M_E     |(A + A^T)/2|_F
+ *   LKS_M_QH    |u . tau_NS|
+ *   LKS_M_QF    |kappa grad T|
+ *   LKS_M_QNSF  |-kappa grad T + u . tau_NS|
+ * Derivatives (a[j+1] - a[j-1]) / (2 dx) with ghost cells by the context's
+ * boundary conditions (periodic: wrap; outflow: repeat the edge cell); dx = 1
+ * on D2Q9 (lattice units), the configured dx on D2Q25.  Inputs: FP64 device
+ * fields [ny][nx] (e.g. those lks_moments writes); T is needed for QF and
+ * QNSF, rho when transport->per_rho.  Transport: mu, lambda, kappa (finite),
+ * each multiplied by the cell's density when per_rho != 0 (D2Q9 in lattice
+ * units: mu = tau c_s^2).  out: FP64 device [popcount(which)][ny][nx], planes
+ * in increasing bit order, distinct from the inputs.  Enqueued on the
+ * context's stream; needs no state (no init). */
+enum {
+    LKS_M_TAU = 1u << 0, LKS_M_C = 1u << 1, LKS_M_S = 1u << 2, LKS_M_E = 1u << 3,
+    LKS_M_QH = 1u << 4, LKS_M_QF = 1u << 5, LKS_M_QNSF = 1u << 6
+};
+typedef struct {
+    double mu, lambda, kappa;
+    int32_t per_rho;
+    int32_t reserved;     /* must be 0 */
+} lks_transport;
+lks_status lks_macro_sensors(lks_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                             const double* T, const lks_transport* transport, uint32_t which,
+                             double* out);
+
 /* ---- Regridding hand-off (Sec. II.B.2, regridding steps 1-2) ----
  * The flag map is turned into refinement patches in three calls: a buffer
  * layer around the tagged cells (the paper uses two buffer cells, Sec. IV),

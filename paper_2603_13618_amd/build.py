@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblks.so")
 SOURCES = ["lks_api.hip", "common.hip", "d2q9.hip", "d2q9_adjoint.hip", "d2q25.hip", "regrid.hip",
-           "cluster.cpp"]
+           "cluster.cpp", "macro.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

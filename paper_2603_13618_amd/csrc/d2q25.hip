@@ -44,11 +44,6 @@
 #ifndef LKS_DDF_WAVES
 #define LKS_DDF_WAVES 2
 #endif
-#if LKS_DDF_WAVES > 0
-#define LKS_DDF_ATTR __attribute__((amdgpu_waves_per_eu(LKS_DDF_WAVES)))
-#else
-#define LKS_DDF_ATTR
-#endif
 
 namespace lks {
 
@@ -440,8 +435,13 @@ __global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typen
 // equilibrium deviations for pass 2.  Pass 2 applies the collision and the
 // fluxes to f; g is then staged into the same buffer and updated.
 // ---------------------------------------------------------------------------
+// the register hint applies to FP32 storage only (FP64 values take two
+// registers each: there the hint would spill hundreds)
+template <typename S> struct DdfWaves { static constexpr int v = 1; };
+template <> struct DdfWaves<float> { static constexpr int v = LKS_DDF_WAVES > 0 ? LKS_DDF_WAVES : 1; };
+
 template <typename S, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_kernel(
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWaves<S>::v))) void d2q25_ddf_kernel(
     D2Q25Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ partials,
     unsigned long long* __restrict__ faults)
@@ -572,8 +572,8 @@ __global__ __launch_bounds__(TX * TY) LKS_DDF_ATTR void d2q25_ddf_kernel(
         klf += (fneq * x) * kl_series(x);
         klg += (gneq * y) * kl_series(y);
         gsum += gneq;
-        nonpos |= !(feq > R(0)) | !(geq > R(0)) | !(x > R(-1)) | !(y > R(-1));
-        far |= !(fabs(x) <= KlCut<R>::v) | !(fabs(y) <= KlCut<R>::v);
+        nonpos = nonpos || !(feq > R(0)) || !(geq > R(0)) || !(x > R(-1)) || !(y > R(-1));
+        far = far || !(fabs(x) <= KlCut<R>::v) || !(fabs(y) <= KlCut<R>::v);
         neq += fabs(fneq) + fabs(gneq);
         pxx += vx * vx * fneq;
         pxy += vx * vy * fneq;

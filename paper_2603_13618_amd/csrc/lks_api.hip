@@ -449,6 +449,39 @@ lks_status lks_check(lks_ctx* c, int64_t* n_nonpos)
     return LKS_OK;
 }
 
+lks_status lks_macro_sensors(lks_ctx* c, const double* rho, const double* ux, const double* uy,
+                             const double* T, const lks_transport* tr, uint32_t which, double* out)
+{
+    if (!c) return LKS_EINVAL;
+    if (!tr) return fail(c, LKS_EINVAL, "transport is NULL");
+    if (tr->reserved != 0) return fail(c, LKS_EINVAL, "transport reserved field must be 0");
+    if (!std::isfinite(tr->mu) || !std::isfinite(tr->lambda) || !std::isfinite(tr->kappa))
+        return fail(c, LKS_EINVAL, "transport coefficients must be finite");
+    if (which == 0 || (which >> lks::kNumMacro) != 0) return fail(c, LKS_EINVAL, "which names no or unknown sensors");
+    if (!ux || !uy || !out) return fail(c, LKS_EINVAL, "ux, uy and out are required");
+    if ((which & (lks::kMacroQF | lks::kMacroQNSF)) && !T) return fail(c, LKS_EINVAL, "T is required for QF and QNSF");
+    if (tr->per_rho && !rho) return fail(c, LKS_EINVAL, "rho is required with per_rho");
+    if (out == ux || out == uy || out == T || out == rho) return fail(c, LKS_EINVAL, "out must not alias an input");
+    const bool aligned8 = aligned(ux, 8) && aligned(uy, 8) && aligned(out, 8) && (!T || aligned(T, 8)) &&
+                          (!rho || aligned(rho, 8));
+    if (!aligned8) return fail(c, LKS_EINVAL, "fields must be 8-byte aligned");
+    lks::MacroArgs a;
+    a.nx = c->cfg.nx;
+    a.ny = c->cfg.ny;
+    a.bc_x = c->cfg.bc_x;
+    a.bc_y = c->cfg.bc_y;
+    a.plane = c->n;
+    a.inv2dx = 0.5 / (c->cfg.lattice == LKS_D2Q9 ? 1.0 : c->cfg.dx);
+    a.mu = tr->mu;
+    a.lam = tr->lambda;
+    a.kappa = tr->kappa;
+    a.per_rho = tr->per_rho ? 1 : 0;
+    a.which = which;
+    int p = 0;
+    for (int k = 0; k < lks::kNumMacro; ++k) a.plane_of[k] = (which & (1u << k)) ? p++ : -1;
+    return hip_check(c, lks::launch_macro(a, rho, ux, uy, T, out, c->stream), "macro sensors");
+}
+
 lks_status lks_tag_buffer(lks_ctx* c, int32_t b, const uint8_t* flags, uint8_t* levels)
 {
     if (!c) return LKS_EINVAL;

@@ -118,6 +118,20 @@ hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream
 
 // regridding hand-off
 constexpr int kMaxBuffer = 8;      // LKS_MAX_BUFFER
+// macroscopic class-1 sensors (central differences)
+constexpr int kNumMacro = 7;
+constexpr unsigned kMacroQF = 1u << 5, kMacroQNSF = 1u << 6;
+struct MacroArgs {
+    int nx, ny, bc_x, bc_y;
+    long long plane;
+    double inv2dx, mu, lam, kappa;
+    int per_rho;
+    unsigned which;
+    int plane_of[kNumMacro];
+};
+hipError_t launch_macro(const MacroArgs& a, const double* rho, const double* ux, const double* uy,
+                        const double* T, double* out, hipStream_t s);
+
 hipError_t launch_tag_buffer(const uint8_t* flags, uint8_t* out, int nx, int ny, int bc_x, int bc_y,
                              int b, hipStream_t s);
 hipError_t launch_tag_tiles(const uint8_t* levels, int* counts, int nx, int ny, int level, int ts,

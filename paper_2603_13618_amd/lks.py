@@ -74,6 +74,14 @@ class Box(ctypes.Structure):
                 ("y1", ctypes.c_int32)]
 
 
+MACRO_NAMES = ("tau", "c", "s", "e", "qh", "qf", "qnsf")
+
+
+class Transport(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("lambda_", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("per_rho", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Buffers(ctypes.Structure):
     _fields_ = [("pop", ctypes.c_void_p * 2), ("sensors", ctypes.c_void_p),
                 ("flags", ctypes.c_void_p), ("sums", ctypes.c_void_p),
@@ -112,6 +120,7 @@ def lib():
             "lks_last_error": ([P], ctypes.c_char_p),
             "lks_copy_probe": ([P, P, ctypes.c_size_t, P], I32),
             "lks_tag_buffer": ([P, I32, P, P], I32),
+            "lks_macro_sensors": ([P, P, P, P, P, ctypes.POINTER(Transport), ctypes.c_uint32, P], I32),
             "lks_tag_tiles": ([P, P, I32, I32, P], I32),
             "lks_cluster": ([P, I32, I32, I32, ctypes.c_double, I32, ctypes.POINTER(Box), I32,
                              ctypes.POINTER(I32)], I32),
@@ -225,6 +234,21 @@ class Lattice:
         st = lib().lks_create(ctypes.byref(self.cfg), ctypes.byref(self.buf),
                               _stream_handle(dev), ctypes.byref(self.ctx))
         _check(st, None)
+
+    def macro_sensors(self, rho, ux, uy, T=None, mu=0.0, lam=0.0, kappa=0.0, per_rho=False,
+                      which=MACRO_NAMES, out=None):
+        """The macroscopic class-1 sensors (central differences) of FP64 device
+        fields [ny, nx]: dict name -> plane of `out` ([len(which), ny, nx] FP64)."""
+        mask = 0
+        for n in which:
+            mask |= 1 << MACRO_NAMES.index(n)
+        names = [n for n in MACRO_NAMES if mask & (1 << MACRO_NAMES.index(n))]
+        if out is None:
+            out = torch.empty((len(names), self.ny, self.nx), dtype=torch.float64, device=self.device)
+        tr = Transport(float(mu), float(lam), float(kappa), 1 if per_rho else 0, 0)
+        _check(lib().lks_macro_sensors(self.ctx, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T),
+                                       ctypes.byref(tr), mask, _ptr(out)), self.ctx)
+        return {n: out[k] for k, n in enumerate(names)}
 
     def tag_buffer(self, b=2, flags=None, out=None):
         """Buffer layer of b cells around the tagged cells of `flags` (default:

@@ -63,7 +63,8 @@ def test_abi_struct_layout_matches_header(tmp_path):
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lks.h\"\nint main(void){\n"
                    + 'printf("%zu %zu", sizeof(lks_config), sizeof(lks_buffers));\n'
                    + "".join(f'printf(" %zu", offsetof(lks_config, {f}));\n' for f in fields)
-                   + 'printf(" %zu %zu\\n", offsetof(lks_buffers, sensors), offsetof(lks_buffers, scratch_bytes));'
+                   + 'printf(" %zu %zu", offsetof(lks_buffers, sensors), offsetof(lks_buffers, scratch_bytes));'
+                   + 'printf(" %zu %zu %zu\\n", sizeof(lks_transport), offsetof(lks_transport, kappa), offsetof(lks_transport, per_rho));'
                    + "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
@@ -73,6 +74,7 @@ def test_abi_struct_layout_matches_header(tmp_path):
     want = [ctypes.sizeof(lks.Config), ctypes.sizeof(lks.Buffers)]
     want += [getattr(lks.Config, f).offset for f in fields]
     want += [lks.Buffers.sensors.offset, lks.Buffers.scratch_bytes.offset]
+    want += [ctypes.sizeof(lks.Transport), lks.Transport.kappa.offset, lks.Transport.per_rho.offset]
     assert got == want
 
 

@@ -28,6 +28,19 @@
 #include "lks_device.h"
 #include "lks_internal.h"
 
+// FP32 workgroup tile (cells) of the single-distribution kernel and the
+// minimum waves per SIMD its register allocation must allow (0 = compiler).
+// Measured at 2048^2: 16 x 8 349 us, 32 x 8 357, 64 x 4 374, 32 x 4 379; a
+// forced four waves per SIMD spills and gains nothing.
+#ifndef LKS_Q25_TX
+#define LKS_Q25_TX 16
+#endif
+#ifndef LKS_Q25_TY
+#define LKS_Q25_TY 8
+#endif
+#ifndef LKS_Q25_WAVES
+#define LKS_Q25_WAVES 0
+#endif
 // FP32 workgroup tile (cells) of the double-distribution kernel and the
 // minimum waves per SIMD its register allocation must allow (0 = compiler's
 // choice).  Measured at 2048^2: left alone the compiler takes ~300 registers
@@ -192,8 +205,11 @@ __device__ __forceinline__ void block_sums_n(double (&acc)[kNsums], double* __re
     }
 }
 
+template <typename S> struct Q25Waves { static constexpr int v = 1; };
+template <> struct Q25Waves<float> { static constexpr int v = LKS_Q25_WAVES > 0 ? LKS_Q25_WAVES : 1; };
+
 template <typename S, int TX, int TY, bool EXT = false>
-__global__ __launch_bounds__(TX * TY) void d2q25_kernel(D2Q25Args a, const typename Store<S>::raw* __restrict__ fin,
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Waves<S>::v))) void d2q25_kernel(D2Q25Args a, const typename Store<S>::raw* __restrict__ fin,
                                                    typename Store<S>::raw* __restrict__ fout,
                                                    typename Store<S>::real* __restrict__ sens,
                                                    uint8_t* __restrict__ flags,
@@ -737,7 +753,7 @@ hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fo
     }
     switch (dtype) {
     case 0: return launch_tile<double, 32, 2>(a, fin, fout, sens, flags, partials, faults, s);
-    case 1: return launch_tile<float, 64, 4>(a, fin, fout, sens, flags, partials, faults, s);
+    case 1: return launch_tile<float, LKS_Q25_TX, LKS_Q25_TY>(a, fin, fout, sens, flags, partials, faults, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -750,8 +766,8 @@ void d2q25_tile_shape(int dtype, int model, int* tx, int* ty)
         *ty = dtype == 0 ? 4 : LKS_DDF_TY;
         return;
     }
-    *tx = dtype == 0 ? 32 : 64;
-    *ty = dtype == 0 ? 2 : 4;
+    *tx = dtype == 0 ? 32 : LKS_Q25_TX;
+    *ty = dtype == 0 ? 2 : LKS_Q25_TY;
 }
 
 // ---------------------------------------------------------------------------

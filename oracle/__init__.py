@@ -21,5 +21,6 @@ from .oracle import (  # noqa: F401
     ddf_moments,
     ddf_step,
     ddf_run,
+    ddf_ext_sensors,
     NSUMS,
 )

@@ -790,6 +790,108 @@ static uint8_t ddf_flag(const double* s, const double* thr, unsigned mask, int f
     return (uint8_t)level;
 }
 
+/* Extension sensors of the double distribution (the rest of Table I with
+ * the g terms superposed, Sec. III; the QE collision of eq. new_collision_fi
+ * as Omega): per cell, literal definitions.
+ *   KN        sum |f^neq/f^eq| + sum |g^neq/g^eq|        (eqs. sensor-Knudsen-kin_f/_g)
+ *   HR        |H(f) - H(f^eq)| + |H(g) - H(g^eq)|, H(h) = sum h ln(h/w)  (eq. Hneq-sensor)
+ *   SIGMA_H   -(sum Omega_f ln(f/w) + sum Omega_g ln(g/w))   (eq. Dissip-H-sensor)
+ *   SIGMA_HKL -(sum Omega_f ln(f/f^eq) + sum Omega_g ln(g/g^eq))  (eq. Dissip-HKL-sensor)
+ *   ALPHA     |2 - alpha_f| + |2 - alpha_g|, the printed polynomial of each  (eqs. sensor-alpha-kin,
+ *             alpha-polynomial-1/2)
+ *   SHEAR     |(1/mu)[(tr P/D) I - P]|, P = sum v v f^neq     (eq. sensor-S-kin)
+ *   QH        |u . P|                                         (eq. sensor-qH-kin)
+ *   QF        |sum v g^neq + sum v |v|^2/2 f^neq - u . P|      (eq. sensor-qF-kin-ryk)
+ *   COMP, STRAIN: 0 (not defined for this model here).
+ * Omega = -(h - h*)/tau1 - (h* - h^eq)/tau2, tau1 = mu/(rho T), tau2 = tau1/Pr.
+ * A positivity fault (any of f, f^eq, g, g^eq not > 0) gives +inf for the
+ * five log/ratio sensors. */
+static void ddf_cell_ext(const orc_rule* r, const double* f, const double* g, double cv, double mu,
+                         double prandtl, double* s)
+{
+    const int D = 2;
+    double fe[25], ge[25], fs[25], gs[25];
+    const orc_ddf_mom m = ddf_moments(r, f, g, cv);
+    ddf_eq_qe(r, &m, cv, fe, ge, fs, gs);
+    const double tau1 = mu / (m.rho * m.T), tau2 = tau1 / prandtl;
+    double kn = 0.0, hf = 0.0, hfe = 0.0, hg = 0.0, hge = 0.0, sh = 0.0, shkl = 0.0;
+    double af[5] = {0, 0, 0, 0, 0}, ag[5] = {0, 0, 0, 0, 0};
+    double pxx = 0.0, pxy = 0.0, pyy = 0.0, qx = 0.0, qy = 0.0;
+    int fault = 0;
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            const int i = 5 * a + b;
+            const double vx = r->v[a], vy = r->v[b], w = r->w[a] * r->w[b];
+            const double fn = f[i] - fe[i], gn = g[i] - ge[i];
+            pxx += vx * vx * fn;
+            pxy += vx * vy * fn;
+            pyy += vy * vy * fn;
+            const double e = 0.5 * (vx * vx + vy * vy);
+            qx += vx * (gn + e * fn);
+            qy += vy * (gn + e * fn);
+            if (!(f[i] > 0.0) || !(fe[i] > 0.0) || !(g[i] > 0.0) || !(ge[i] > 0.0)) {
+                fault = 1;
+                continue;
+            }
+            const double of = -(f[i] - fs[i]) / tau1 - (fs[i] - fe[i]) / tau2;
+            const double og = -(g[i] - gs[i]) / tau1 - (gs[i] - ge[i]) / tau2;
+            kn += fabs(fn / fe[i]) + fabs(gn / ge[i]);
+            hf += f[i] * log(f[i] / w);
+            hfe += fe[i] * log(fe[i] / w);
+            hg += g[i] * log(g[i] / w);
+            hge += ge[i] * log(ge[i] / w);
+            sh -= of * log(f[i] / w) + og * log(g[i] / w);
+            shkl -= of * log(f[i] / fe[i]) + og * log(g[i] / ge[i]);
+            for (int n = 1; n <= 4; ++n) {
+                af[n] += pow(fn, n + 1) / pow(f[i], n);
+                ag[n] += pow(gn, n + 1) / pow(g[i], n);
+            }
+        }
+    double adev = 0.0;
+    for (int k = 0; k < 2; ++k) {
+        double* an = k ? ag : af;
+        for (int n = 1; n <= 4; ++n) an[n] *= ((n % 2) ? 1.0 : -1.0) / (n * (n + 1.0));
+        if (an[1] != 0.0) {
+            const double r2 = an[2] / an[1], r3 = an[3] / an[1], r4 = an[4] / an[1];
+            const double alpha = 2.0 - 4.0 * r2 + 16.0 * r2 * r2 - 8.0 * r3 + 80.0 * r2 * r3
+                                 - 80.0 * r2 * r2 * r2 - 16.0 * r4;
+            adev += fabs(2.0 - alpha);
+        }
+    }
+    const double tr = pxx + pyy;
+    const double sxx = (tr / D - pxx) / mu, syy = (tr / D - pyy) / mu, sxy = -pxy / mu;
+    const double hx = m.ux * pxx + m.uy * pxy, hy = m.ux * pxy + m.uy * pyy;
+    s[ORC_X_KN] = fault ? INFINITY : kn;
+    s[ORC_X_HR] = fault ? INFINITY : fabs(hf - hfe) + fabs(hg - hge);
+    s[ORC_X_SIGMA_H] = fault ? INFINITY : sh;
+    s[ORC_X_SIGMA_HKL] = fault ? INFINITY : shkl;
+    s[ORC_X_ALPHA] = fault ? INFINITY : adev;
+    s[ORC_X_SHEAR] = sqrt(sxx * sxx + 2.0 * sxy * sxy + syy * syy);
+    s[ORC_X_QH] = sqrt(hx * hx + hy * hy);
+    s[ORC_X_QF] = sqrt((qx - hx) * (qx - hx) + (qy - hy) * (qy - hy));
+    s[ORC_X_COMP] = 0.0;
+    s[ORC_X_STRAIN] = 0.0;
+}
+
+/* extension sensors of n cells of a double-distribution state [50][n]:
+ * out [ORC_NEXT][n] */
+int orc_ddf_ext_sensors(long n, const double* f, double cv, double mu, double prandtl, double* out)
+{
+    orc_rule r;
+    rule_d2q25(&r);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) {
+        double fc[25], gc[25], s[ORC_NEXT];
+        for (int i = 0; i < 25; ++i) {
+            fc[i] = f[(long)i * n + c];
+            gc[i] = f[(long)(25 + i) * n + c];
+        }
+        ddf_cell_ext(&r, fc, gc, cv, mu, prandtl, s);
+        for (int k = 0; k < ORC_NEXT; ++k) out[(long)k * n + c] = s[k];
+    }
+    return 0;
+}
+
 /* equilibrium (f^eq, g^eq) of n cells from FP64 fields: out [50][n] */
 int orc_ddf_equilibrium(long n, const double* rho, const double* ux, const double* uy,
                         const double* T, double cv, double* out)

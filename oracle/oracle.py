@@ -67,6 +67,7 @@ def _load():
                                     ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_uint, P,
                                     ctypes.c_int]
         lib.orc_ddf_run.restype = ctypes.c_long
+        lib.orc_ddf_ext_sensors.argtypes = [ctypes.c_long, P, D, D, D, P]
         lib.orc_num_ext.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -158,6 +159,17 @@ def ddf_moments(f, gamma=1.4, qe=False):
     q = np.empty((100,) + f.shape[1:]) if qe else None
     _load().orc_ddf_moments(n, _p(f), cv_of(gamma), _p(out), _p(q))
     return (out, q) if qe else out
+
+
+def ddf_ext_sensors(f, mu, gamma=1.4, prandtl=0.71):
+    """The extension sensors [len(EXT_NAMES), *shape] of a double-distribution
+    state f [50, *shape] (g terms superposed, QE collision; COMP and STRAIN
+    are 0)."""
+    f = _f64(f)
+    n = f[0].size
+    out = np.empty((len(EXT_NAMES),) + f.shape[1:])
+    _load().orc_ddf_ext_sensors(n, _p(f), cv_of(gamma), float(mu), float(prandtl), _p(out))
+    return out
 
 
 def _thr5(thr):

@@ -36,7 +36,7 @@ FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 # the double-distribution step (FP32): 50 x 4 read + 50 x 4 written + 5 x 4
 # sensors + 1 flag per cell
 BYTES_F32_DDF = 421
-DDF_KERNEL = "d2q25_ddf_kernel<float,16,8>"
+DDF_KERNEL = "d2q25_ddf_kernel<float,16,8,false>"
 
 
 def parse():
@@ -57,7 +57,7 @@ def parse():
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
     p.add_argument("--workload", choices=["smooth4096", "riemann2048", "smooth8192-bf16",
                                           "smooth8192-f16", "adjoint1024", "smooth4096-ext",
-                                          "riemann2048-ext", "riemann2048-ddf"],
+                                          "riemann2048-ext", "riemann2048-ddf", "riemann2048-ddf-ext"],
                    default="smooth4096", help="workload of --mode kernel (profiling runs)")
     p.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                    help="assemble the traffic summary from four rocprofv3 --pmc output "
@@ -380,12 +380,15 @@ def ext_lattices(lks, inputs, workloads, dev, steps):
 
 
 def time_ext(torch, lks, inputs, workloads, dev, ev):
-    """Fused steps with every extension sensor on (timing only)."""
+    """Fused steps with every extension sensor on (timing only): D2Q9, the
+    single and the double distribution on D2Q25."""
     k = 40
     a, b = ext_lattices(lks, inputs, workloads, dev, k)
+    c = ddf_lattice(lks, inputs, workloads, dev, k, ext=EXT25)
     res = {}
     for name, lat, nbytes in (("d2q9_4096_f32_ext9", a, 85 + 4 * len(EXT9)),
-                              ("d2q25_2048_f32_ext8", b, 217 + 4 * len(EXT25))):
+                              ("d2q25_2048_f32_ext8", b, 217 + 4 * len(EXT25)),
+                              ("d2q25_ddf_2048_f32_ext8", c, BYTES_F32_DDF + 4 * len(EXT25))):
         lat.step(3)
         torch.cuda.synchronize()
         s, e = ev(), ev()
@@ -398,13 +401,14 @@ def time_ext(torch, lks, inputs, workloads, dev, ev):
         res[name] = {"MLUPS": round(cells / t / 1e6, 1), "us_per_step": round(t * 1e6, 1),
                      "GBps_model": round(nbytes * cells / t / 1e9, 1), "bytes_per_lup": nbytes,
                      "faults": lat.check()}
-    del a, b
+    del a, b, c
     torch.cuda.empty_cache()
     return res
 
 
-def ddf_lattice(lks, inputs, workloads, dev, steps):
-    """The double-distribution workload, initialised (FP32 storage)."""
+def ddf_lattice(lks, inputs, workloads, dev, steps, ext=None):
+    """The double-distribution workload, initialised (FP32 storage), with the
+    extension sensors `ext` if given."""
     wl = workloads.RIEMANN_2048_DDF
     n = wl["nx"]
     rho, ux, uy, T, states = inputs.riemann_quadrants(n, seed=wl["seed"])
@@ -412,7 +416,7 @@ def ddf_lattice(lks, inputs, workloads, dev, steps):
     lat = lks.Lattice(25, n, n, "f32", mu=wl["mu"], dt=inputs.riemann_dt(states, dx, gamma=wl["gamma"]),
                       dx=dx, bc=(1, 1), thr=wl["thr"], flag_mask=wl["flag_mask"],
                       max_steps=max(steps, 1), model="ddf", gamma=wl["gamma"],
-                      prandtl=wl["prandtl"], thr_qe=wl["thr_qe"], device=dev)
+                      prandtl=wl["prandtl"], thr_qe=wl["thr_qe"], ext=ext, device=dev)
     lat.init(rho, ux, uy, T)
     return lat
 
@@ -451,7 +455,9 @@ def time_ddf(torch, lks, inputs, workloads, dev, ev):
 
 def kernel_only(args, torch, lks, inputs, workloads, dev):
     """A short run of one of the other workloads (for profilers)."""
-    if args.workload.endswith("-ext"):
+    if args.workload == "riemann2048-ddf-ext":
+        ddf_lattice(lks, inputs, workloads, dev, args.steps, ext=EXT25).step(args.steps)
+    elif args.workload.endswith("-ext"):
         a, b = ext_lattices(lks, inputs, workloads, dev, args.steps)
         (a if args.workload.startswith("smooth") else b).step(args.steps)
     elif args.workload == "riemann2048-ddf":

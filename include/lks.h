@@ -108,11 +108,17 @@ enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u, LKS_S_QE = 16
  *                  sensor-qNSF-kin-ryk, Sensor-qe-kin); S_QE drives flag bit
  *                  LKS_S_QE with thresholds thr_qe.  A positivity fault is any
  *                  f, f^eq, g or g^eq not > 0.  The energy sum is E.  F32 or
- *                  F64 storage, fused steps, no extension sensors. */
+ *                  F64 storage, fused steps.  Extension sensors (LKS_X_*,
+ *                  planes after the five base planes) take the g terms
+ *                  superposed and the QE collision as Omega: KN, HR, SIGMA_H,
+ *                  SIGMA_HKL and ALPHA add the g form of each to the f form,
+ *                  QF is |sum v g^neq + sum v |v|^2/2 f^neq - u . P|; SHEAR and
+ *                  QH are those of f; COMP and STRAIN are not available. */
 enum { LKS_MODEL_BGK = 0, LKS_MODEL_DDF = 1 };
 
 /* Extension sensors (bit k of ext_mask), the rest of Table I evaluated on the
- * f distribution in the same pass, on the pre-collision populations; BGK
+ * f distribution in the same pass (with LKS_MODEL_DDF: f and g, see there),
+ * on the pre-collision populations; BGK
  * collision Omega_i = -(f_i - f^eq_i)/tau, P = sum v v f^neq, q^neq =
  * sum v |v|^2/2 f^neq, u = sum v f / sum f; D2Q9 in lattice units with
  * mu = tau rho c_s^2 (c_s^2 = 1/3) and lambda = 0, D2Q25 with the configured

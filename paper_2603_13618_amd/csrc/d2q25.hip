@@ -131,8 +131,11 @@ __device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& 
 #pragma unroll
         for (int m = 1; m < 5; ++m) sy[b][m] = sy[b][m - 1] + hy[m] * R(gh5_he(b, m));
     }
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
+    // the population loops are unrolled by templates: a pragma gives up when
+    // the caller's per-population body is large, and the callers index
+    // register arrays by the population
+    sfor25<5>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
         R px[5];
         R pt = R(0);
         px[0] = R(1);
@@ -141,14 +144,14 @@ __device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& 
             px[n] = hx[n] * R(gh5_he(a, n));
             pt += px[n];
         }
-#pragma unroll
-        for (int b = 0; b < 5; ++b) {
+        sfor25<5>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
             R s = pt + sy[b][4];
 #pragma unroll
             for (int n = 1; n < 4; ++n) s += px[n] * sy[b][4 - n];
             use(a, b, R(gh5_w(a) * gh5_w(b)) * (rho * s + drho));
-        }
-    }
+        });
+    });
 }
 
 // half van Leer slope ab/(a+b) for same-sign a, b, else 0
@@ -456,7 +459,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
 template <typename S> struct DdfWaves { static constexpr int v = 1; };
 template <> struct DdfWaves<float> { static constexpr int v = LKS_DDF_WAVES > 0 ? LKS_DDF_WAVES : 1; };
 
-template <typename S, int TX, int TY>
+template <typename S, int TX, int TY, bool EXT = false>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWaves<S>::v))) void d2q25_ddf_kernel(
     D2Q25Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ partials,
@@ -622,6 +625,92 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         });
     }
 
+    // q^neq through an opaque copy in both instantiations: the extension's use
+    // of it must not change how the compiler contracts S_Q
+    const R qxo = pin(qx), qyo = pin(qy);
+
+    // ---- extension sensors (the rest of Table I with the g terms): a pass
+    //      of their own on opaque copies (pin) of the moments and populations,
+    //      so the base arithmetic is the same with and without them.  The QE
+    //      parts of the dissipations, sum (h* - h^eq)_i L_i, are q . sum c_i v_i L_i
+    //      with c_i = w_i (|v_i|^2/4 - 1) for f and w_i for g.
+    R xv[EXT ? kNumExt : 1];
+    if constexpr (EXT) {
+        const R drho_p = pin(drho), rho_p = pin(rho), ux_p = pin(ux), uy_p = pin(uy), tm1_p = pin(tm1),
+                rho0_p = pin(rho0), gfac_p = pin(gfac);
+        const R Tc_p = R(1) + tm1_p;
+        const ExtNeed need(a.x.mask);
+        const bool needV = a.x.mask & 0x4u, needW = a.x.mask & 0x8u;
+        ExtAcc<R> ef, eg;
+        R vfx = R(0), vfy = R(0), wfx = R(0), wfy = R(0), vgx = R(0), vgy = R(0), wgx = R(0), wgy = R(0);
+        d2q25_deq<R>(drho_p, rho_p, ux_p, uy_p, tm1_p, [&](int ia, int ib, R deq) {
+            const int i = 5 * ia + ib;
+            const R w = R(gh5_w(ia) * gh5_w(ib));
+            const R iw = R(1.0 / (gh5_w(ia) * gh5_w(ib)));
+            const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+            const R d = pin(fc[i]), dg = pin(gc[i]);
+            const R feq = w * rho0_p + deq, fneq = d - deq, x = fneq * rcp(feq);
+            const R tf = (rho0_p - R(1)) + deq * iw;                    // f^eq/w - 1
+            ef.add(need, fneq, x, w * rho0_p + d, tf);
+            const R dgeq = gfac_p * (Tc_p * deq + tm1_p * (w * rho0_p));
+            const R geq = gfac_p * (w * rho0_p) + dgeq, gneq = dg - dgeq, y = gneq * rcp(geq);
+            const R tg = (gfac_p * rho0_p - R(1)) + dgeq * iw;           // g^eq/w - 1
+            eg.add(need, gneq, y, gfac_p * (w * rho0_p) + dg, tg);
+            if (needV || needW) {
+                const R cf = w * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
+                const R lxf = ln1p_fast(x), lxg = ln1p_fast(y);
+                if (needV) {                                   // ln(h/w) = ln(h^eq/w) + ln(1 + x)
+                    const R lf = ln1p_fast(tf) + lxf, lg = ln1p_fast(tg) + lxg;
+                    vfx += cf * vx * lf;
+                    vfy += cf * vy * lf;
+                    vgx += w * vx * lg;
+                    vgy += w * vy * lg;
+                }
+                if (needW) {                                   // ln(h/h^eq) = ln(1 + x)
+                    wfx += cf * vx * lxf;
+                    wfy += cf * vy * lxf;
+                    wgx += w * vx * lxg;
+                    wgy += w * vy * lxg;
+                }
+            }
+        });
+        const R inf = R(INFINITY);
+        const bool fault_p = nonpos || !(fabs(klf) + fabs(klg + gsum) == fabs(klf) + fabs(klg + gsum));
+        const R inv_mu = R(1.0 / a.mu);
+        const R inv_tau1 = rho_p * Tc_p * inv_mu;
+        const R d12 = inv_tau1 * (R(1) - R(a.prandtl));                  // 1/tau1 - 1/tau2
+        const R qfx_p = pin(qfx), qfy_p = pin(qfy), qgx_p = pin(qgx), qgy_p = pin(qgy);
+        auto alpha_dev = [](const ExtAcc<R>& e) {
+            R dev = R(0);
+            if (e.a1 != R(0)) {
+                const R ia1 = rcp(R(0.5) * e.a1);
+                const R r2 = R(-1.0 / 6.0) * e.a2 * ia1, r3 = R(1.0 / 12.0) * e.a3 * ia1,
+                        r4 = R(-1.0 / 20.0) * e.a4 * ia1;
+                dev = R(4) * r2 - R(16) * r2 * r2 + R(8) * r3 - R(80) * r2 * r3 + R(80) * r2 * r2 * r2 + R(16) * r4;
+            }
+            return fabs(dev);
+        };
+        // H(f) - H(f^eq) = sum f ln(f/f^eq) + sum f^neq ln(f^eq/w); the same for g
+        const R hkf = pin(klf), hkg = pin(klg) + pin(gsum);
+        xv[0] = fault_p ? inf : ef.kn + eg.kn;
+        xv[1] = fault_p ? inf : fabs(hkf + ef.L) + fabs(hkg + eg.L);
+        xv[2] = fault_p ? inf
+                        : inv_tau1 * (ef.shkl + ef.L + eg.shkl + eg.L) -
+                              d12 * (qfx_p * vfx + qfy_p * vfy + qgx_p * vgx + qgy_p * vgy);
+        xv[3] = fault_p ? inf
+                        : inv_tau1 * (ef.shkl + eg.shkl) - d12 * (qfx_p * wfx + qfy_p * wfy + qgx_p * wgx + qgy_p * wgy);
+        xv[4] = fault_p ? inf : alpha_dev(ef) + alpha_dev(eg);
+        const R pxx_p = pin(pxx), pxy_p = pin(pxy), pyy_p = pin(pyy);
+        const R dxy = pxx_p - pyy_p;
+        xv[5] = inv_mu * sqrt(R(0.5) * dxy * dxy + R(2) * pxy_p * pxy_p);
+        const R hx = ux_p * pxx_p + uy_p * pxy_p, hy = ux_p * pxy_p + uy_p * pyy_p;
+        xv[6] = sqrt(hx * hx + hy * hy);
+        const R fx = qxo - hx, fy = qyo - hy;
+        xv[7] = sqrt(fx * fx + fy * fy);
+        xv[8] = R(0);
+        xv[9] = R(0);
+    }
+
     // ---- pass 2: f' = f - A div - (dt/tau1)(f - f^eq) + (dt/tau1 - dt/tau2)(f* - f^eq),
     //      f first, then g through the same buffer
     const R A = R(a.dt / a.dx);
@@ -680,7 +769,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     const bool fault = nonpos || !(klsum == klsum);
     const R s_kl = fault ? R(INFINITY) : klsum;
     const R s_pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
-    const R s_q = sqrt(qx * qx + qy * qy);
+    const R s_q = sqrt(qxo * qxo + qyo * qyo);
     double acc[kNsums];
 #pragma unroll
     for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
@@ -695,6 +784,16 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
                 const int l = (sv[s] > t0) + (sv[s] > t1);
                 level = l > level ? l : level;
             }
+        }
+        if constexpr (EXT) {
+            sfor25<kNumExt>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if (a.x.plane[q] >= 0) sens[a.x.plane[q] * plane + off] = xv[q];
+                if (a.mask & (1u << (kExtFlagShift + q))) {
+                    const int l = (xv[q] > R(a.x.thr[q][0])) + (xv[q] > R(a.x.thr[q][1]));
+                    level = l > level ? l : level;
+                }
+            });
         }
 #pragma unroll
         for (int s = 0; s < 5; ++s) sens[s * plane + off] = sv[s];
@@ -720,8 +819,12 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
     using raw = typename Store<S>::raw;
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
-    d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
-        a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    if (a.x.mask)
+        d2q25_ddf_kernel<S, TX, TY, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else
+        d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     return hipGetLastError();
 }
 

@@ -237,8 +237,6 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
         return fail(nullptr, LKS_EUNSUPPORTED, "D2Q25 supports F32 and F64 storage");
     if (cfg->ext_mask && cfg->dtype != LKS_F32 && cfg->dtype != LKS_F64)
         return fail(nullptr, LKS_EUNSUPPORTED, "extension sensors need F32 or F64 storage");
-    if (cfg->ext_mask && ddf(*cfg))
-        return fail(nullptr, LKS_EUNSUPPORTED, "extension sensors are BGK-model only");
     if (!buf->pop[0] || !buf->pop[1] || !buf->sensors || !buf->flags || !buf->sums || !buf->scratch)
         return fail(nullptr, LKS_EINVAL, "a buffer pointer is NULL");
     if (buf->pop[0] == buf->pop[1]) return fail(nullptr, LKS_EINVAL, "pop[0] and pop[1] alias");

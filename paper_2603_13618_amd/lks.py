@@ -270,7 +270,7 @@ class Lattice:
         k = EXT_NAMES.index(name)
         if not self.ext_mask & (1 << k):
             raise KeyError(name)
-        base = int(lib().lks_num_sensors(self.cfg.lattice))
+        base = 5 if self.model == MODEL_DDF else int(lib().lks_num_sensors(self.cfg.lattice))
         return self.sensors[base + bin(self.ext_mask & ((1 << k) - 1)).count("1")]
 
     def __del__(self):

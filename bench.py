@@ -34,9 +34,10 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2603_13618_amd", "csrc", "d2q9.hip")
 FUSED_KERNEL = "d2q9_fused_lds<float,4,false>"
 FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 # the double-distribution step (FP32): 50 x 4 read + 50 x 4 written + 5 x 4
-# sensors + 1 flag per cell
+# sensors + 1 flag per cell (the method's bytes; the two kernels of the step
+# also hand 6 values per cell over and read g's own cell twice: 569 B)
 BYTES_F32_DDF = 421
-DDF_KERNEL = "d2q25_ddf_kernel<float,16,8,false>"
+DDF_KERNEL = "d2q25_ddf_kernel<float,16,8,false> + d2q25_ddf_g_kernel<float,16,8>"
 
 
 def parse():

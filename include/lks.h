@@ -192,7 +192,8 @@ typedef struct {
 } lks_buffers;
 
 /* Device bytes of scratch the configuration needs (per-block FP64 partial
- * sums and counters).  0 for an invalid configuration. */
+ * sums and counters; with LKS_MODEL_DDF also 6 values per cell that the
+ * step's f kernel hands to its g kernel).  0 for an invalid configuration. */
 size_t lks_scratch_bytes(const lks_config* cfg);
 
 /* Number of base sensor planes of a lattice with the BGK model (3 for D2Q9,

@@ -746,22 +746,22 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const R divf = div_of(lds + i * T::kPlane, d, ia, ib, vx, vy);
         if (active) fout[i * plane + off] = Store<S>::from_real(d - A * divf - B1 * fneq + B12 * dfs);
     });
-    __syncthreads();              // every f read of the buffer is done
-    stage(25, gc, true);
-    __syncthreads();
+    // g* - g^eq = w (q_g . v): its part of the QE sensor; g itself is updated
+    // by d2q25_ddf_g_kernel from the cell state handed over here
     sfor25<25>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ia = i / 5, ib = i % 5;
-        const R w = R(gh5_w(ia) * gh5_w(ib));
-        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
-        const R dg = gc[i];
-        const R gneq = dg - gfac * (Tc * deqv[i] + tm1 * (w * rho0));
-        // g* - g^eq = w (q_g . v)
-        const R dgs = w * (qgx * vx + qgy * vy);
-        qe += fabs(dgs);
-        const R divg = div_of(lds + i * T::kPlane, dg, ia, ib, vx, vy);
-        if (active) fout[(25 + i) * plane + off] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
+        qe += fabs(R(gh5_w(ia) * gh5_w(ib)) * (qgx * R(gh5_xi(ia)) + qgy * R(gh5_xi(ib))));
     });
+    if (active) {
+        R* aux = static_cast<R*>(a.aux) + off;
+        aux[0] = drho;
+        aux[plane] = ux;
+        aux[2 * plane] = uy;
+        aux[3 * plane] = tm1;
+        aux[4 * plane] = qgx;
+        aux[5 * plane] = qgy;
+    }
 
     // sum f ln(f/f^eq) = sum f^eq phi(x) (f and f^eq carry the same mass);
     // sum g ln(g/g^eq) = sum g^eq phi(y) + sum g^neq
@@ -811,6 +811,135 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     block_sums_n<NT / kWave>(acc, partials + (long long)blockIdx.x * kNsums);
 }
 
+// The g update of the double distribution: g is staged with its halo like
+// f in d2q25_ddf_kernel, the cell state comes from that kernel's hand-over
+// (drho, u, T - 1, q_g), and the collision and fluxes are those of f:
+// g' = g - A div - (dt/tau1)(g - g^eq) + (dt/tau1 - dt/tau2)(g* - g^eq).
+// Splitting the step here keeps the f kernel within two waves per SIMD
+// without spilling registers.
+template <typename S, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
+                                                         const typename Store<S>::raw* __restrict__ fin,
+                                                         typename Store<S>::raw* __restrict__ fout)
+{
+    using R = typename Store<S>::real;
+    using T = Tile<TX, TY>;
+    constexpr int NT = TX * TY;
+    __shared__ R lds[25 * T::kPlane];
+
+    const int nx = a.nx, ny = a.ny;
+    const long long plane = a.plane;
+    int tile_x, tile_y;
+    {
+        const int b = blockIdx.x;
+        if (a.tiles_x % 8 == 0) {
+            const int bw = a.tiles_x / 8, l = b / 8;
+            tile_x = (b % 8) * bw + l % bw;
+            tile_y = l / bw;
+        } else {
+            tile_x = b % a.tiles_x;
+            tile_y = b / a.tiles_x;
+        }
+    }
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int X0 = tile_x * TX, Y0 = tile_y * TY;
+    const int X = X0 + tx, Y = Y0 + ty;
+    const bool active = X < nx && Y < ny;
+    const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
+
+    constexpr int HR = (4 * TX + NT - 1) / NT;
+    const long long own = (long long)gyc * nx + gxc;
+    long long hoff[HR];
+    int hlds[HR];
+#pragma unroll
+    for (int k = 0; k < HR; ++k) {
+        const int h = threadIdx.x + k * NT;
+        const int hr = h / TX, c = h % TX;
+        const int r = hr < 2 ? hr - 2 : TY + hr - 2;
+        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
+    }
+    long long coff = 0;
+    int clds = -1;
+    if (threadIdx.x < 4 * TY) {
+        const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
+        const int c = hc < 2 ? hc - 2 : TX + hc - 2;
+        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        clds = T::rowbase(r) + c;
+    }
+    const int olds = T::rowbase(ty) + tx;
+    const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
+                       T::rowbase(ty + 2)};
+    const long long off = (long long)Y * nx + X;
+
+    // the cell state from the f kernel (own cell only; ghost threads stage)
+    R drho = R(0), ux = R(0), uy = R(0), tm1 = R(0), qgx = R(0), qgy = R(0);
+    if (active) {
+        const R* aux = static_cast<const R*>(a.aux) + off;
+        drho = aux[0];
+        ux = aux[plane];
+        uy = aux[2 * plane];
+        tm1 = aux[3 * plane];
+        qgx = aux[4 * plane];
+        qgy = aux[5 * plane];
+    }
+
+    R gc[25];
+    {
+        R vh[HR][25], vc[25];
+        sfor25<25>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const typename Store<S>::raw* src = fin + (25 + i) * plane;
+            gc[i] = Store<S>::to_real(src[own]);
+#pragma unroll
+            for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
+            vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
+        });
+        sfor25<25>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            R* dst = lds + i * T::kPlane;
+            dst[olds] = gc[i];
+#pragma unroll
+            for (int k = 0; k < HR; ++k)
+                if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];
+            if (clds >= 0) dst[clds] = vc[i];
+        });
+    }
+    __syncthreads();
+
+    const R rho0 = R(a.rho0);
+    const R gfac = R(a.cv) - R(1);
+    const R rho = rho0 + drho;
+    const R Tc = R(1) + tm1;
+    const R A = R(a.dt / a.dx);
+    const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
+    const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
+    const int own_lds = rb[2] + tx;
+    auto div_of = [&](const R* t, R d, int ia, int ib, R vx, R vy) {
+        R div = R(0);
+        if (ia != 2) {
+            const R* row = t + own_lds;
+            div += vx * (ia > 2 ? flux_diff<R, 1>(row[-2], row[-1], d, row[1], R(0))
+                                : flux_diff<R, -1>(R(0), row[-1], d, row[1], row[2]));
+        }
+        if (ib != 2) {
+            div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
+                                : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
+        }
+        return div;
+    };
+    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+        const int i = 5 * ia + ib;
+        const R w = R(gh5_w(ia) * gh5_w(ib));
+        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+        const R dg = gc[i];
+        const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
+        const R dgs = w * (qgx * vx + qgy * vy);
+        const R divg = div_of(lds + i * T::kPlane, dg, ia, ib, vx, vy);
+        if (active) fout[(25 + i) * plane + off] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
+    });
+}
+
 template <typename S, int TX, int TY>
 static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fout, void* sens,
                                   uint8_t* flags, double* partials, unsigned long long* faults,
@@ -819,12 +948,15 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
     using raw = typename Store<S>::raw;
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
+    if (!a.aux) return hipErrorInvalidValue;
     if (a.x.mask)
         d2q25_ddf_kernel<S, TX, TY, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     else
         d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    d2q25_ddf_g_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(a, (const raw*)fin, (raw*)fout);
     return hipGetLastError();
 }
 

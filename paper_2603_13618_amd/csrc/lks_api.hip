@@ -142,6 +142,7 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
     a.prandtl = ddf(c) ? c.prandtl : 1.0;
     a.thr_qe[0] = ddf(c) ? c.thr_qe[0] : 0.0;
     a.thr_qe[1] = ddf(c) ? c.thr_qe[1] : 0.0;
+    a.aux = nullptr;
     lks::d2q25_tile_shape(c.dtype, c.model, &a.tile_x, &a.tile_y);
     a.tiles_x = (c.nx + a.tile_x - 1) / a.tile_x;
     a.tiles_y = (c.ny + a.tile_y - 1) / a.tile_y;
@@ -167,10 +168,21 @@ int chunk_steps(const lks_config& c)
     return (int)k;
 }
 
-size_t scratch_for(const lks_config& c)
+size_t partials_bytes(const lks_config& c)
 {
-    return kHeader + (size_t)chunk_steps(c) * (size_t)step_blocks(c) * lks::kNsumsHost * sizeof(double);
+    const size_t b = (size_t)chunk_steps(c) * (size_t)step_blocks(c) * lks::kNsumsHost * sizeof(double);
+    return (b + 255) / 256 * 256;
 }
+
+// the double distribution's per-cell hand-over between its two kernels
+size_t aux_bytes(const lks_config& c)
+{
+    if (!ddf(c)) return 0;
+    const size_t real = c.dtype == LKS_F64 ? 8 : 4;
+    return (size_t)lks::kDdfAux * (size_t)c.nx * (size_t)c.ny * real;
+}
+
+size_t scratch_for(const lks_config& c) { return kHeader + partials_bytes(c) + aux_bytes(c); }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -265,6 +277,7 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     c->chunk = chunk_steps(*cfg);
     c->faults = reinterpret_cast<unsigned long long*>(buf->scratch);
     c->partials = reinterpret_cast<double*>(static_cast<char*>(buf->scratch) + kHeader);
+    void* aux = aux_bytes(*cfg) ? static_cast<char*>(buf->scratch) + kHeader + partials_bytes(*cfg) : nullptr;
 
     // widest vector the row length and buffer alignment allow (or the hint)
     int vec = cfg->launch_vec > 0 ? cfg->launch_vec : wide_vec(cfg->dtype);
@@ -287,6 +300,7 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
         for (int k = 0; k < 2; ++k) a.thr_f[s][k] = (float)cfg->thr[s][k];
     a.x = ext_args(*cfg);
     c->a25 = d2q25_args(*cfg);
+    c->a25.aux = aux;
     c->nblocks = cfg->lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
     *out = c;
     return LKS_OK;

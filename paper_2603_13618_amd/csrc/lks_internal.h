@@ -63,7 +63,11 @@ struct D2Q25Args {
     double cv;                // C_v = R/(gamma - 1)
     double prandtl;           // Pr = tau1/tau2 (<= 1)
     double thr_qe[2];         // thresholds of the quasi-equilibrium sensor
+    // per-cell hand-over of the double distribution's f pass to its g pass:
+    // [6][plane] of drho, ux, uy, T - 1, q_g (x, y) in the compute type
+    void* aux;
 };
+constexpr int kDdfAux = 6;
 
 // D2Q9 passes: the fused step and the three passes of the unfused baseline
 enum Pass { kFused = 0, kStream = 1, kSense = 2, kCollide = 3 };

@@ -41,11 +41,10 @@
 #ifndef LKS_Q25_WAVES
 #define LKS_Q25_WAVES 0
 #endif
-// FP32 workgroup tile (cells) of the double-distribution kernel and the
-// minimum waves per SIMD its register allocation must allow (0 = compiler's
-// choice).  Measured at 2048^2: left alone the compiler takes ~300 registers
-// (one wave per SIMD); forcing two waves spills ~60 of them to scratch (cache
-// resident) and is 1.2x faster; three spill far more and are 2x slower.
+// FP32 workgroup tile (cells) of the double-distribution kernels and the
+// minimum waves per SIMD the f kernel's register allocation must allow (0 =
+// compiler's choice).  Left alone the compiler gives the f kernel a budget
+// of one wave per SIMD; two waves fit without spilling (three spill).
 // Narrow tiles let more workgroups share a CU across the barriers and 16 x 8
 // stages the fewest halo cells per cell of the shapes that fit.
 #ifndef LKS_DDF_TX

@@ -2,10 +2,11 @@
 MI355X, against the unfused passes, the HBM roofline and the FP64 CPU oracle.
 
 Workload: smooth random field (seed 0, 16 Fourier modes), D2Q9 BGK, 4096x4096
-periodic, tau = 0.52, FP32 deviation storage; one step = pull streaming +
+periodic, tau = 0.52, FP32 deviation storage in the row-interleaved layout
+([ny][9][nx]; --layout planes for [9][ny][nx]); one step = pull streaming +
 moments + equilibrium + S_KL, S_NEQ, S_PI + refinement flags + BGK collision +
-FP64 global sums, all in one kernel (plus one small reduction kernel per 64
-steps).  Inputs are resident in HBM before the timed region starts.
+FP64 global sums, all in one kernel (plus one small reduction kernel per
+batch of steps).  Inputs are resident in HBM before the timed region starts.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--forms]
     python bench.py --mode kernel --steps 5      # short run for profilers
@@ -38,6 +39,7 @@ FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 # also hand 6 values per cell over and read g's own cell twice: 569 B)
 BYTES_F32_DDF = 421
 DDF_KERNEL = "d2q25_ddf_kernel<float,16,8,false> + d2q25_ddf_g_kernel<float,16,8>"
+LAYOUT = "rows"                 # population layout of every lattice (--layout)
 
 
 def parse():
@@ -55,6 +57,9 @@ def parse():
                    help="also time the D2Q25 double-distribution step on the 2048^2 Riemann problem")
     p.add_argument("--regrid", action="store_true",
                    help="also time the regridding hand-off on the final flag map")
+    p.add_argument("--layout", choices=["planes", "rows"], default="rows",
+                   help="population layout of every lattice: plane-major [Q][ny][nx] or "
+                        "row-interleaved [ny][Q][nx]")
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
     p.add_argument("--workload", choices=["smooth4096", "riemann2048", "smooth8192-bf16",
                                           "smooth8192-f16", "adjoint1024", "smooth4096-ext",
@@ -68,8 +73,9 @@ def parse():
 
 
 def kernel_hash():
+    # the kernel source and the launch-shape and layout code around it
     h = hashlib.sha256()
-    for name in ("d2q9.hip", "lks_device.h"):
+    for name in ("d2q9.hip", "lks_device.h", "lks_internal.h", "lks_api.hip"):
         with open(os.path.join(ROOT, "paper_2603_13618_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -82,7 +88,8 @@ def traffic_entry(n_cells):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
-    if t.get("kernel_hash") != kernel_hash() or t.get("cells") != n_cells:
+    if (t.get("kernel_hash") != kernel_hash() or t.get("cells") != n_cells
+            or t.get("layout", "planes") != LAYOUT):
         return None
     return t.get("bytes_per_launch")
 
@@ -110,6 +117,7 @@ def assemble_traffic(dirs):
     from paper_2603_13618_amd import workloads
     n = workloads.SMOOTH_4096["nx"]
     copy_bytes = 9 * n * n * 4
+    lay = [] if LAYOUT == "rows" else ["--layout", LAYOUT]
     fetch, nf = _pmc_mean(dirs[0], "FETCH_SIZE", FUSED_KERNEL_PREFIX)
     write, nw = _pmc_mean(dirs[1], "WRITE_SIZE", FUSED_KERNEL_PREFIX)
     cfetch, _ = _pmc_mean(dirs[2], "FETCH_SIZE", "copy_kernel")
@@ -119,7 +127,7 @@ def assemble_traffic(dirs):
     read_b = fetch * 1024.0 * kf
     write_b = write * 1024.0 * kw
     out = {
-        "kernel": FUSED_KERNEL, "cells": n * n, "kernel_hash": kernel_hash(),
+        "kernel": FUSED_KERNEL, "cells": n * n, "kernel_hash": kernel_hash(), "layout": LAYOUT,
         "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
         "copy_fetch_kib": cfetch, "copy_write_kib": cwrite, "copy_bytes_each_way": copy_bytes,
         "fetch_scale": kf, "write_scale": kw,
@@ -127,16 +135,16 @@ def assemble_traffic(dirs):
         "bytes_per_launch": read_b + write_b,
         "algorithmic_bytes_per_launch": BYTES_F32_FUSED * n * n,
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE -T -d <dir> -o fetch --output-format csv -- "
-            "python bench.py --mode kernel --steps 3",
-            "rocprofv3 --pmc WRITE_SIZE -T -d <dir> -o write --output-format csv -- "
-            "python bench.py --mode kernel --steps 3",
+            " ".join(["rocprofv3 --pmc FETCH_SIZE -T -d <dir> -o fetch --output-format csv --",
+                      "python bench.py --mode kernel --steps 3"] + lay),
+            " ".join(["rocprofv3 --pmc WRITE_SIZE -T -d <dir> -o write --output-format csv --",
+                      "python bench.py --mode kernel --steps 3"] + lay),
             "rocprofv3 --pmc FETCH_SIZE -T -d <dir> -o cfetch --output-format csv -- "
             "python bench.py --mode copy",
             "rocprofv3 --pmc WRITE_SIZE -T -d <dir> -o cwrite --output-format csv -- "
             "python bench.py --mode copy",
-            "python bench.py --traffic-from <fetch dir> <write dir> <copy fetch dir> "
-            "<copy write dir>",
+            " ".join(["python bench.py --traffic-from <fetch dir> <write dir> <copy fetch dir>",
+                      "<copy write dir>"] + lay),
         ],
     }
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
@@ -146,7 +154,9 @@ def assemble_traffic(dirs):
 
 
 def main():
+    global LAYOUT
     args = parse()
+    LAYOUT = args.layout
     if args.traffic_from:
         assemble_traffic(args.traffic_from)
         return
@@ -187,7 +197,7 @@ def main():
 
     rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
     lat = lks.Lattice(9, n, n, "f32", tau=wl["tau"], thr=wl["thr"], flag_mask=wl["flag_mask"],
-                      max_steps=max(args.steps, 1), device=dev)
+                      max_steps=max(args.steps, 1), layout=LAYOUT, device=dev)
     lat.init(rho, ux, uy)
 
     if args.mode == "kernel":
@@ -258,7 +268,7 @@ def main():
             "workload": "D2Q9 BGK 4096x4096 periodic, FP32 deviation storage, fused pull-stream "
                         "+ collide + S_KL/S_NEQ/S_PI + flags + FP64 sums, tau=0.52, smooth "
                         "random field (seed 0, 16 modes)",
-            "grid": [n, n], "tau": wl["tau"], "lattice": "D2Q9",
+            "grid": [n, n], "tau": wl["tau"], "lattice": "D2Q9", "layout": LAYOUT,
         },
         "achieved_GBps": round(BYTES_F32_FUSED * n * n / t_step / 1e9, 1),
         "roofline": {
@@ -367,7 +377,7 @@ def ext_lattices(lks, inputs, workloads, dev, steps):
     n = wl["nx"]
     rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
     a = lks.Lattice(9, n, n, "f32", tau=wl["tau"], thr=wl["thr"], flag_mask=wl["flag_mask"],
-                    max_steps=max(steps, 1), ext=EXT9, device=dev)
+                    max_steps=max(steps, 1), ext=EXT9, layout=LAYOUT, device=dev)
     a.init(rho, ux, uy)
     wq = workloads.RIEMANN_2048
     m = wq["nx"]
@@ -375,7 +385,7 @@ def ext_lattices(lks, inputs, workloads, dev, steps):
     dx = 1.0 / m
     b = lks.Lattice(25, m, m, "f32", mu=wq["mu"], dt=inputs.riemann_dt(states, dx), dx=dx,
                     bc=(1, 1), thr=wq["thr"], flag_mask=wq["flag_mask"], max_steps=max(steps, 1),
-                    ext=EXT25, device=dev)
+                    ext=EXT25, layout=LAYOUT, device=dev)
     b.init(rho, ux, uy, T)
     return a, b
 
@@ -417,7 +427,7 @@ def ddf_lattice(lks, inputs, workloads, dev, steps, ext=None):
     lat = lks.Lattice(25, n, n, "f32", mu=wl["mu"], dt=inputs.riemann_dt(states, dx, gamma=wl["gamma"]),
                       dx=dx, bc=(1, 1), thr=wl["thr"], flag_mask=wl["flag_mask"],
                       max_steps=max(steps, 1), model="ddf", gamma=wl["gamma"],
-                      prandtl=wl["prandtl"], thr_qe=wl["thr_qe"], ext=ext, device=dev)
+                      prandtl=wl["prandtl"], thr_qe=wl["thr_qe"], ext=ext, layout=LAYOUT, device=dev)
     lat.init(rho, ux, uy, T)
     return lat
 
@@ -470,7 +480,7 @@ def kernel_only(args, torch, lks, inputs, workloads, dev):
         dx = 1.0 / n
         lat = lks.Lattice(25, n, n, "f32", mu=wl["mu"], dt=inputs.riemann_dt(states, dx), dx=dx,
                           bc=(1, 1), thr=wl["thr"], flag_mask=wl["flag_mask"],
-                          max_steps=max(args.steps, 1), device=dev)
+                          max_steps=max(args.steps, 1), layout=LAYOUT, device=dev)
         lat.init(rho, ux, uy, T)
         lat.step(args.steps)
     elif args.workload.startswith("smooth8192"):
@@ -478,7 +488,7 @@ def kernel_only(args, torch, lks, inputs, workloads, dev):
         n = wl["nx"]
         rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
         lat = lks.Lattice(9, n, n, args.workload.split("-")[1], tau=wl["tau"], thr=wl["thr"],
-                          flag_mask=wl["flag_mask"], max_steps=max(args.steps, 1), device=dev)
+                          flag_mask=wl["flag_mask"], max_steps=max(args.steps, 1), layout=LAYOUT, device=dev)
         lat.init(rho, ux, uy)
         lat.step(args.steps)
     else:
@@ -489,7 +499,8 @@ def kernel_only(args, torch, lks, inputs, workloads, dev):
         u = torch.tensor(ux, device=dev, requires_grad=True)
         v = torch.tensor(uy, device=dev, requires_grad=True)
         L = adjoint.kl_sensor_loss(u, v, torch.tensor(rho, device=dev), tau=wl["tau"],
-                                   nsteps=args.steps, checkpoint=wl["checkpoint"], dtype="f32")
+                                   nsteps=args.steps, checkpoint=wl["checkpoint"], dtype="f32",
+                                   layout=LAYOUT)
         L.backward()
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernel", "workload": args.workload, "steps": args.steps}))
@@ -503,7 +514,7 @@ def time_forms(torch, lks, inputs, workloads, dev, ev):
     res = {}
     for dtype, nbytes in (("bf16", 49), ("f16", 49), ("f32", 85)):
         lat = lks.Lattice(9, n, n, dtype, tau=wl["tau"], thr=wl["thr"] or workloads.SMOOTH_4096["thr"],
-                          flag_mask=wl["flag_mask"], max_steps=64, device=dev)
+                          flag_mask=wl["flag_mask"], max_steps=64, layout=LAYOUT, device=dev)
         lat.init(rho, ux, uy)
         lat.step(5)
         torch.cuda.synchronize()

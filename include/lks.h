@@ -21,7 +21,13 @@
  *     (the LKS_X_* extension sensors below).
  *
  * Conventions
- *   Layout: structure of arrays, plane-major [k][ny][nx], x fastest.
+ *   Layout: structure of arrays, x fastest.  Sensors, flags and fields are
+ *     plane-major [k][ny][nx].  Populations follow the configured layout:
+ *     LKS_LAYOUT_PLANES [Q][ny][nx] (f_i(x, y) at element (i*ny + y)*nx + x)
+ *     or LKS_LAYOUT_ROWS [ny][Q][nx] (at (y*Q + i)*nx + x: the Q rows of one
+ *     grid row lie together, so a step touches a few long runs of HBM
+ *     instead of one run per population plane).  Both layouts hold the
+ *     same values and every kernel gives bit-identical results on them.
  *     Population index i = q1*a + b, a = x-node, b = y-node index (ascending),
  *     q1 = 3 or 5.  D2Q9 velocity i is (a-1, b-1).
  *   Storage: populations are stored as deviations d_i = f_i - w_i*rho0 in the
@@ -81,6 +87,7 @@ typedef enum {
 enum { LKS_D2Q9 = 9, LKS_D2Q25 = 25 };
 enum { LKS_F64 = 0, LKS_F32 = 1, LKS_BF16 = 2, LKS_F16 = 3 };
 enum { LKS_PERIODIC = 0, LKS_OUTFLOW = 1 };
+enum { LKS_LAYOUT_PLANES = 0, LKS_LAYOUT_ROWS = 1 };
 enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u, LKS_S_QE = 16u };
 
 /* Kinetic model of a D2Q25 lattice (D2Q9 is always LKS_MODEL_BGK).
@@ -174,15 +181,17 @@ typedef struct {
     double thr_ext[LKS_MAX_EXT][2]; /* (theta1 <= theta2) per extension sensor,
                              used when its LKS_FLAG_X bit is in flag_mask      */
     int32_t model;        /* LKS_MODEL_BGK (0) or, on D2Q25, LKS_MODEL_DDF     */
-    int32_t model_reserved; /* must be 0                                        */
+    int32_t layout;       /* population layout, LKS_LAYOUT_PLANES (0) or
+                             LKS_LAYOUT_ROWS (see Conventions)                 */
     double gamma;         /* LKS_MODEL_DDF: adiabatic exponent, 1 < gamma < 2  */
     double prandtl;       /* LKS_MODEL_DDF: Prandtl number, 0 < Pr <= 1        */
     double thr_qe[2];     /* LKS_MODEL_DDF: (theta1 <= theta2) of S_QE         */
 } lks_config;
 
 typedef struct {
-    void* pop[2];         /* [Q][ny][nx] dtype, ping-pong state buffers (Q = 50
-                             with LKS_MODEL_DDF)                               */
+    void* pop[2];         /* Q*ny*nx values of dtype in the configured layout,
+                             ping-pong state buffers (Q = 50 with
+                             LKS_MODEL_DDF)                                    */
     void* sensors;        /* [lks_sensor_planes(cfg)][ny][nx] float (double for
                              F64): base planes, then the extension planes     */
     uint8_t* flags;       /* [ny][nx]                                          */
@@ -252,7 +261,8 @@ lks_status lks_check(lks_ctx* ctx, int64_t* n_nonpos);
 /* ---- Adjoint of the D2Q9 step (gradient of the summed smooth KL sensor) ----
  * Loss L = sum_x S_KL(g_N(x)), g_N the pre-collision populations of the last
  * step N, initial populations at the equilibrium of (rho0, u0).  All arrays
- * are device [9][ny][nx] in the context's dtype (F32 or F64) unless stated.
+ * are device populations (9 per cell, the context's layout and dtype, F32 or
+ * F64) unless stated.
  *   seed:  lam_out = dL/dg_N, from pop_prev = f_{N-1} (the state before step N)
  *   step:  lam_out = dL/dg_n = J_C(g_n)^T S^T lam_in, lam_in = dL/dg_{n+1},
  *          pop_prev = f_{n-1}; J_C is the BGK collision Jacobian and S^T the

@@ -21,12 +21,12 @@ from . import lks
 
 class _KLSensorLoss(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, ux0, uy0, rho0, tau, nsteps, checkpoint, dtype):
+    def forward(ctx, ux0, uy0, rho0, tau, nsteps, checkpoint, dtype, layout):
         if nsteps < 1 or checkpoint < 1:
             raise ValueError("nsteps and checkpoint must be >= 1")
         ny, nx = ux0.shape
         dev = ux0.device
-        lat = lks.Lattice(9, nx, ny, dtype, tau=tau, max_steps=nsteps, device=dev)
+        lat = lks.Lattice(9, nx, ny, dtype, tau=tau, max_steps=nsteps, layout=layout, device=dev)
         lat.init(rho0, ux0.detach(), uy0.detach())
         ckpts = {0: lat.state.clone()}
         done = 0
@@ -48,8 +48,8 @@ class _KLSensorLoss(torch.autograd.Function):
         lat, ckpts = ctx.lat, ctx.ckpts
         nsteps, K = ctx.meta
         rho0, ux0, uy0 = ctx.fields
-        seg = [torch.empty_like(lat.pop[0]) for _ in range(min(K, nsteps))]
-        lam = [torch.empty_like(lat.pop[0]) for _ in range(2)]
+        seg = [lat.new_state() for _ in range(min(K, nsteps))]
+        lam = [lat.new_state() for _ in range(2)]
         cur = 0                      # lam[cur] holds dL/dg_{n+1} entering step n
         for s in sorted(ckpts, reverse=True):
             e = min(s + K - 1, nsteps - 1)          # states f_s .. f_e
@@ -67,11 +67,13 @@ class _KLSensorLoss(torch.autograd.Function):
         guy = torch.empty_like(uy0)
         lat.adjoint_init(rho0, ux0, uy0, lam[cur], gux, guy)
         g = grad_out.to(torch.float64)
-        return gux * g, guy * g, None, None, None, None, None
+        return gux * g, guy * g, None, None, None, None, None, None
 
 
-def kl_sensor_loss(ux0, uy0, rho0, tau=0.52, nsteps=200, checkpoint=20, dtype="f32"):
+def kl_sensor_loss(ux0, uy0, rho0, tau=0.52, nsteps=200, checkpoint=20, dtype="f32",
+                   layout="planes"):
     """L = sum of the smooth KL sensor at the last of nsteps steps (0-dim
     float64 tensor), differentiable w.r.t. ux0 and uy0 ([ny, nx] float64 CUDA
-    tensors); rho0 is held fixed."""
-    return _KLSensorLoss.apply(ux0, uy0, rho0, tau, nsteps, checkpoint, dtype)
+    tensors); rho0 is held fixed.  layout: the population layout of the
+    states the forward and reverse steps run on."""
+    return _KLSensorLoss.apply(ux0, uy0, rho0, tau, nsteps, checkpoint, dtype, layout)

@@ -13,8 +13,10 @@
 // h_n(u, theta) = E[He_n(X)], X ~ N(u, theta); sensors and sums are taken on
 // f^n, the state the collision reads.
 //
-// Layout and staging: SoA planes [25][ny][nx] of deviations d_i = f_i - w_i rho0
-// (the constant part cancels in every flux difference).  A TX x TY workgroup
+// Layout and staging: deviations d_i = f_i - w_i rho0 (the constant part
+// cancels in every flux difference), population i of cell (x, y) at
+// i * pp + y * pr + x (PopLayout: plane-major [25][ny][nx] or row-interleaved
+// [ny][25][nx]).  A TX x TY workgroup
 // tile stages all 25 planes of its cells plus a two-cell cross-shaped halo in
 // LDS once, then every stencil read comes from LDS.  Tiles are assigned to
 // workgroups so that the eight XCDs each sweep their own band of tile
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     //      population plane): its own cell, up to HR halo-row cells and one
     //      halo-column cell
     constexpr int HR = (4 * TX + NT - 1) / NT;
-    long long own = (long long)gyc * nx + gxc;
+    long long own = (long long)gyc * a.L.pr + gxc;
     long long hoff[HR];
     int hlds[HR];
 #pragma unroll
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
         const int h = threadIdx.x + k * NT;
         const int hr = h / TX, c = h % TX;
         const int r = hr < 2 ? hr - 2 : TY + hr - 2;
-        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
         hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
     }
     long long coff = 0;
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     if (threadIdx.x < 4 * TY) {
         const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
         const int c = hc < 2 ? hc - 2 : TX + hc - 2;
-        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
         clds = T::rowbase(r) + c;
     }
     const int olds = T::rowbase(ty) + tx;
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     R vin[25], vh[HR][25], vc[25];
     sfor25<25>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const typename Store<S>::raw* src = fin + i * plane;
+        const typename Store<S>::raw* src = fin + i * a.L.pp;
         vin[i] = Store<S>::to_real(src[own]);
 #pragma unroll
         for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
@@ -318,6 +320,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     R xmin = R(0), xmax = R(0), feqmin = R(0);
     bool first = true;
     const long long off = (long long)Y * nx + X;
+    const long long poff = a.L.at(0, Y, X);
     d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
         const int i = 5 * ia + ib;
         const R* t = lds + i * T::kPlane;
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
             div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
                                 : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
         }
-        if (active) fout[i * plane + off] = Store<S>::from_real(d - A * div + B * (deq - d));
+        if (active) fout[i * a.L.pp + poff] = Store<S>::from_real(d - A * div + B * (deq - d));
     });
     if (!(xmax <= KlCut<R>::v)) {
         // rare: some population far from equilibrium (or NaN): the closed form
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
 
     constexpr int HR = (4 * TX + NT - 1) / NT;
-    const long long own = (long long)gyc * nx + gxc;
+    const long long own = (long long)gyc * a.L.pr + gxc;
     long long hoff[HR];
     int hlds[HR];
 #pragma unroll
@@ -498,7 +501,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const int h = threadIdx.x + k * NT;
         const int hr = h / TX, c = h % TX;
         const int r = hr < 2 ? hr - 2 : TY + hr - 2;
-        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
         hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
     }
     long long coff = 0;
@@ -506,7 +509,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     if (threadIdx.x < 4 * TY) {
         const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
         const int c = hc < 2 ? hc - 2 : TX + hc - 2;
-        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
         clds = T::rowbase(r) + c;
     }
     const int olds = T::rowbase(ty) + tx;
@@ -519,7 +522,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         R vh[HR][25], vc[25];
         sfor25<25>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            const typename Store<S>::raw* src = fin + (p0 + i) * plane;
+            const typename Store<S>::raw* src = fin + (p0 + i) * a.L.pp;
             if (!own_loaded) own_v[i] = Store<S>::to_real(src[own]);
 #pragma unroll
             for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     R fc[25], gc[25];
     sfor25<25>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        gc[i] = Store<S>::to_real(fin[(25 + i) * plane + own]);
+        gc[i] = Store<S>::to_real(fin[(25 + i) * a.L.pp + own]);
     });
     stage(0, fc, false);
 
@@ -716,6 +719,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
     const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
     const long long off = (long long)Y * nx + X;
+    const long long poff = a.L.at(0, Y, X);
     const int own_lds = rb[2] + tx;
     __syncthreads();              // the staged f of the whole tile (pass 1 read registers only)
     auto div_of = [&](const R* t, R d, int ia, int ib, R vx, R vy) {
@@ -743,7 +747,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const R dfs = w * (qfx * vx + qfy * vy) * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
         qe += fabs(dfs);
         const R divf = div_of(lds + i * T::kPlane, d, ia, ib, vx, vy);
-        if (active) fout[i * plane + off] = Store<S>::from_real(d - A * divf - B1 * fneq + B12 * dfs);
+        if (active) fout[i * a.L.pp + poff] = Store<S>::from_real(d - A * divf - B1 * fneq + B12 * dfs);
     });
     // g* - g^eq = w (q_g . v): its part of the QE sensor; g itself is updated
     // by d2q25_ddf_g_kernel from the cell state handed over here
@@ -847,7 +851,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
     const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
 
     constexpr int HR = (4 * TX + NT - 1) / NT;
-    const long long own = (long long)gyc * nx + gxc;
+    const long long own = (long long)gyc * a.L.pr + gxc;
     long long hoff[HR];
     int hlds[HR];
 #pragma unroll
@@ -855,7 +859,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
         const int h = threadIdx.x + k * NT;
         const int hr = h / TX, c = h % TX;
         const int r = hr < 2 ? hr - 2 : TY + hr - 2;
-        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
         hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
     }
     long long coff = 0;
@@ -863,13 +867,14 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
     if (threadIdx.x < 4 * TY) {
         const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
         const int c = hc < 2 ? hc - 2 : TX + hc - 2;
-        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * nx + ghost_index(X0 + c, nx, a.bc_x);
+        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
         clds = T::rowbase(r) + c;
     }
     const int olds = T::rowbase(ty) + tx;
     const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
                        T::rowbase(ty + 2)};
     const long long off = (long long)Y * nx + X;
+    const long long poff = a.L.at(0, Y, X);
 
     // the cell state from the f kernel (own cell only; ghost threads stage)
     R drho = R(0), ux = R(0), uy = R(0), tm1 = R(0), qgx = R(0), qgy = R(0);
@@ -888,7 +893,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
         R vh[HR][25], vc[25];
         sfor25<25>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            const typename Store<S>::raw* src = fin + (25 + i) * plane;
+            const typename Store<S>::raw* src = fin + (25 + i) * a.L.pp;
             gc[i] = Store<S>::to_real(src[own]);
 #pragma unroll
             for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
@@ -935,7 +940,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
         const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
         const R dgs = w * (qgx * vx + qgy * vy);
         const R divg = div_of(lds + i * T::kPlane, dg, ia, ib, vx, vy);
-        if (active) fout[(25 + i) * plane + off] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
+        if (active) fout[(25 + i) * a.L.pp + poff] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
     });
 }
 
@@ -1008,7 +1013,7 @@ void d2q25_tile_shape(int dtype, int model, int* tx, int* ty)
 // Equilibrium initialiser and moment readout (one thread per cell, FP64 math)
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ __launch_bounds__(kBlock) void d2q25_init_kernel(long long n, double rho0, const double* __restrict__ rho,
+__global__ __launch_bounds__(kBlock) void d2q25_init_kernel(long long n, PopLayout L, double rho0, const double* __restrict__ rho,
                                                        const double* __restrict__ ux,
                                                        const double* __restrict__ uy,
                                                        const double* __restrict__ T,
@@ -1018,12 +1023,12 @@ __global__ __launch_bounds__(kBlock) void d2q25_init_kernel(long long n, double 
     if (c >= n) return;
     const double r = rho[c];
     d2q25_deq<double>(r - rho0, r, ux[c], uy[c], T[c] - 1.0, [&](int ia, int ib, double deq) {
-        pop[(5 * ia + ib) * n + c] = Store<S>::from_real((typename Store<S>::real)deq);
+        pop[L.cell(5 * ia + ib, c)] = Store<S>::from_real((typename Store<S>::real)deq);
     });
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void d2q25_moments_kernel(long long n, double rho0,
+__global__ __launch_bounds__(kBlock) void d2q25_moments_kernel(long long n, PopLayout L, double rho0,
                                                           const typename Store<S>::raw* __restrict__ pop,
                                                           double* __restrict__ rho, double* __restrict__ ux,
                                                           double* __restrict__ uy, double* __restrict__ T)
@@ -1033,7 +1038,7 @@ __global__ __launch_bounds__(kBlock) void d2q25_moments_kernel(long long n, doub
     double drho = 0.0, jx = 0.0, jy = 0.0, edev = 0.0;
 #pragma unroll
     for (int i = 0; i < 25; ++i) {
-        const double d = (double)Store<S>::to_real(pop[i * n + c]);
+        const double d = (double)Store<S>::to_real(pop[L.cell(i, c)]);
         const double vx = gh5_xi(i / 5), vy = gh5_xi(i % 5);
         drho += d;
         jx += vx * d;
@@ -1050,7 +1055,7 @@ __global__ __launch_bounds__(kBlock) void d2q25_moments_kernel(long long n, doub
 
 // double distribution: f^eq and g^eq = (C_v - 1) T f^eq as deviations
 template <typename S>
-__global__ __launch_bounds__(kBlock) void d2q25_ddf_init_kernel(long long n, double rho0, double cv,
+__global__ __launch_bounds__(kBlock) void d2q25_ddf_init_kernel(long long n, PopLayout L, double rho0, double cv,
                                                            const double* __restrict__ rho,
                                                            const double* __restrict__ ux,
                                                            const double* __restrict__ uy,
@@ -1063,14 +1068,14 @@ __global__ __launch_bounds__(kBlock) void d2q25_ddf_init_kernel(long long n, dou
     d2q25_deq<double>(r - rho0, r, ux[c], uy[c], t - 1.0, [&](int ia, int ib, double deq) {
         const int i = 5 * ia + ib;
         const double w = gh5_w(ia) * gh5_w(ib);
-        pop[i * n + c] = Store<S>::from_real((typename Store<S>::real)deq);
+        pop[L.cell(i, c)] = Store<S>::from_real((typename Store<S>::real)deq);
         const double dgeq = (cv - 1.0) * (t * deq + (t - 1.0) * w * rho0);
-        pop[(25 + i) * n + c] = Store<S>::from_real((typename Store<S>::real)dgeq);
+        pop[L.cell(25 + i, c)] = Store<S>::from_real((typename Store<S>::real)dgeq);
     });
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void d2q25_ddf_moments_kernel(long long n, double rho0, double cv,
+__global__ __launch_bounds__(kBlock) void d2q25_ddf_moments_kernel(long long n, PopLayout L, double rho0, double cv,
                                                               const typename Store<S>::raw* __restrict__ pop,
                                                               double* __restrict__ rho,
                                                               double* __restrict__ ux,
@@ -1082,13 +1087,13 @@ __global__ __launch_bounds__(kBlock) void d2q25_ddf_moments_kernel(long long n, 
     double drho = 0.0, jx = 0.0, jy = 0.0, m2 = 0.0, dg0 = 0.0;
 #pragma unroll
     for (int i = 0; i < 25; ++i) {
-        const double d = (double)Store<S>::to_real(pop[i * n + c]);
+        const double d = (double)Store<S>::to_real(pop[L.cell(i, c)]);
         const double vx = gh5_xi(i / 5), vy = gh5_xi(i % 5);
         drho += d;
         jx += vx * d;
         jy += vy * d;
         m2 += (vx * vx + vy * vy) * d;
-        dg0 += (double)Store<S>::to_real(pop[(25 + i) * n + c]);
+        dg0 += (double)Store<S>::to_real(pop[L.cell(25 + i, c)]);
     }
     const double r = rho0 + drho;
     const double u = jx / r, v = jy / r;
@@ -1098,50 +1103,50 @@ __global__ __launch_bounds__(kBlock) void d2q25_ddf_moments_kernel(long long n, 
     if (T) T[c] = 1.0 + ((dg0 + 0.5 * m2 - cv * drho) / r - 0.5 * (u * u + v * v)) / cv;
 }
 
-hipError_t launch_d2q25_ddf_init(int dtype, long long n, double rho0, double cv, const double* rho,
+hipError_t launch_d2q25_ddf_init(int dtype, long long n, const PopLayout& L, double rho0, double cv, const double* rho,
                                  const double* ux, const double* uy, const double* T, void* pop,
                                  hipStream_t s)
 {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     switch (dtype) {
-    case 0: d2q25_ddf_init_kernel<double><<<grid, block, 0, s>>>(n, rho0, cv, rho, ux, uy, T, (double*)pop); break;
-    case 1: d2q25_ddf_init_kernel<float><<<grid, block, 0, s>>>(n, rho0, cv, rho, ux, uy, T, (float*)pop); break;
+    case 0: d2q25_ddf_init_kernel<double><<<grid, block, 0, s>>>(n, L, rho0, cv, rho, ux, uy, T, (double*)pop); break;
+    case 1: d2q25_ddf_init_kernel<float><<<grid, block, 0, s>>>(n, L, rho0, cv, rho, ux, uy, T, (float*)pop); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_d2q25_ddf_moments(int dtype, long long n, double rho0, double cv, const void* pop,
+hipError_t launch_d2q25_ddf_moments(int dtype, long long n, const PopLayout& L, double rho0, double cv, const void* pop,
                                     double* rho, double* ux, double* uy, double* T, hipStream_t s)
 {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     switch (dtype) {
-    case 0: d2q25_ddf_moments_kernel<double><<<grid, block, 0, s>>>(n, rho0, cv, (const double*)pop, rho, ux, uy, T); break;
-    case 1: d2q25_ddf_moments_kernel<float><<<grid, block, 0, s>>>(n, rho0, cv, (const float*)pop, rho, ux, uy, T); break;
+    case 0: d2q25_ddf_moments_kernel<double><<<grid, block, 0, s>>>(n, L, rho0, cv, (const double*)pop, rho, ux, uy, T); break;
+    case 1: d2q25_ddf_moments_kernel<float><<<grid, block, 0, s>>>(n, L, rho0, cv, (const float*)pop, rho, ux, uy, T); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_d2q25_init(int dtype, long long n, double rho0, const double* rho, const double* ux,
+hipError_t launch_d2q25_init(int dtype, long long n, const PopLayout& L, double rho0, const double* rho, const double* ux,
                              const double* uy, const double* T, void* pop, hipStream_t s)
 {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     switch (dtype) {
-    case 0: d2q25_init_kernel<double><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, T, (double*)pop); break;
-    case 1: d2q25_init_kernel<float><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, T, (float*)pop); break;
+    case 0: d2q25_init_kernel<double><<<grid, block, 0, s>>>(n, L, rho0, rho, ux, uy, T, (double*)pop); break;
+    case 1: d2q25_init_kernel<float><<<grid, block, 0, s>>>(n, L, rho0, rho, ux, uy, T, (float*)pop); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_d2q25_moments(int dtype, long long n, double rho0, const void* pop, double* rho,
+hipError_t launch_d2q25_moments(int dtype, long long n, const PopLayout& L, double rho0, const void* pop, double* rho,
                                 double* ux, double* uy, double* T, hipStream_t s)
 {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     switch (dtype) {
-    case 0: d2q25_moments_kernel<double><<<grid, block, 0, s>>>(n, rho0, (const double*)pop, rho, ux, uy, T); break;
-    case 1: d2q25_moments_kernel<float><<<grid, block, 0, s>>>(n, rho0, (const float*)pop, rho, ux, uy, T); break;
+    case 0: d2q25_moments_kernel<double><<<grid, block, 0, s>>>(n, L, rho0, (const double*)pop, rho, ux, uy, T); break;
+    case 1: d2q25_moments_kernel<float><<<grid, block, 0, s>>>(n, L, rho0, (const float*)pop, rho, ux, uy, T); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

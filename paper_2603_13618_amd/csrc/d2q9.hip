@@ -8,9 +8,11 @@
 // S_NEQ (eq. sensor-neq-kin) and S_PI (eq. sensor-TauNS-kin) on the
 // pre-collision populations, refinement flags (Sec. II.B.2, step 1).
 //
-// Memory layout: SoA planes [9][ny][nx] of deviations d_i = f_i - w_i rho0.
-// One thread owns VEC consecutive cells of a row, so every population plane is
-// read with one aligned VEC-wide load per thread; the x-shifted populations
+// Memory layout: deviations d_i = f_i - w_i rho0, population i of cell (x, y)
+// at i * pp + y * pr + x (PopLayout: plane-major [9][ny][nx] or
+// row-interleaved [ny][9][nx], x fastest in both).  One thread owns VEC
+// consecutive cells of a row, so every population row is read with one
+// aligned VEC-wide load per thread; the x-shifted populations
 // take their one missing neighbour from the adjacent lane (ds_bpermute) and
 // only the wave's edge lanes touch memory for it.  Pull streaming reads each
 // stored value exactly once, so HBM traffic is one read and one write per
@@ -205,7 +207,7 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
 }
 
 template <typename S, int VEC, bool PULL>
-__device__ __forceinline__ void load_row(const typename Store<S>::raw* __restrict__ fin, long long plane,
+__device__ __forceinline__ void load_row(const typename Store<S>::raw* __restrict__ fin, const PopLayout& L,
                                          int y, int nx, int ny, int x0, bool active, int lane,
                                          typename Store<S>::real (&d)[9][VEC])
 {
@@ -217,7 +219,7 @@ __device__ __forceinline__ void load_row(const typename Store<S>::raw* __restric
         int ys = y - cy;
         ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
         R v[VEC];
-        pull_row<cx, S, VEC>(fin + i * plane + (long long)ys * nx, x0, nx, active, lane, v);
+        pull_row<cx, S, VEC>(fin + L.at(i, ys, 0), x0, nx, active, lane, v);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) d[i][k] = v[k];
     });
@@ -267,16 +269,17 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
     R ring[PF + 1][9][VEC];
 #pragma unroll
     for (int p = 0; p < PF; ++p)
-        if (y0 + p < y1) load_row<S, VEC, PULL>(fin, plane, y0 + p, nx, ny, x0, active, lane, ring[p]);
+        if (y0 + p < y1) load_row<S, VEC, PULL>(fin, a.L, y0 + p, nx, ny, x0, active, lane, ring[p]);
     for (int y = y0; y < y1; ++y) {                 // uniform across the workgroup
-        if (y + PF < y1) load_row<S, VEC, PULL>(fin, plane, y + PF, nx, ny, x0, active, lane, ring[PF]);
+        if (y + PF < y1) load_row<S, VEC, PULL>(fin, a.L, y + PF, nx, ny, x0, active, lane, ring[PF]);
         R (&cur)[9][VEC] = ring[0];
         const long long off = (long long)y * nx + x0;
+        const long long poff = a.L.at(0, y, x0);
 
         if constexpr (PASS == kStream) {
             if (active) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, cur[i]);
+                for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * a.L.pp + poff, cur[i]);
             }
         } else {
             R s_kl[VEC], s_neq[VEC], s_pi[VEC];
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
             if (active) {
                 if constexpr (COLLIDE) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, cur[i]);
+                    for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * a.L.pp + poff, cur[i]);
                 }
                 if constexpr (SENSE) {
                     store_pack<R, VEC>(sens + off, s_kl);
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             constexpr int cx = cx9(i), cy = cy9(i);
             int ys = y - cy;
             ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-            const raw* row = fin + i * plane + (long long)ys * nx;
+            const raw* row = fin + a.L.at(i, ys, 0);
             if (active) {
 #pragma unroll
                 for (int p = 0; p < G::NP; ++p) {
@@ -466,8 +469,9 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     auto store_row = [&](int y) {
         if (active) {
             const long long off = (long long)y * nx + x0;
+            const long long poff = a.L.at(0, y, x0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * plane + off, res[i]);
+            for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * a.L.pp + poff, res[i]);
             store_pack<R, VEC>(sens + off, s_kl);
             store_pack<R, VEC>(sens + plane + off, s_neq);
             store_pack<R, VEC>(sens + 2 * plane + off, s_pi);
@@ -657,7 +661,7 @@ hipError_t launch_d2q9(int dtype, int pass, const D2Q9Args& a, const void* fin, 
 // Equilibrium initialiser and moment readout (one thread per cell, FP64 math)
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ __launch_bounds__(kBlock) void d2q9_init_kernel(long long n, double rho0, const double* __restrict__ rho,
+__global__ __launch_bounds__(kBlock) void d2q9_init_kernel(long long n, PopLayout L, double rho0, const double* __restrict__ rho,
                                                       const double* __restrict__ ux,
                                                       const double* __restrict__ uy,
                                                       typename Store<S>::raw* __restrict__ pop)
@@ -670,12 +674,12 @@ __global__ __launch_bounds__(kBlock) void d2q9_init_kernel(long long n, double r
     for (int i = 0; i < 9; ++i) {
         const double cu = cx9(i) * u + cy9(i) * v;
         const double deq = w9<double>(i) * ((r - rho0) + r * (cu * (3.0 + 4.5 * cu) - usq15));
-        pop[i * n + c] = Store<S>::from_real((typename Store<S>::real)deq);
+        pop[L.cell(i, c)] = Store<S>::from_real((typename Store<S>::real)deq);
     }
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void d2q9_moments_kernel(long long n, double rho0,
+__global__ __launch_bounds__(kBlock) void d2q9_moments_kernel(long long n, PopLayout L, double rho0,
                                                          const typename Store<S>::raw* __restrict__ pop,
                                                          double* __restrict__ rho, double* __restrict__ ux,
                                                          double* __restrict__ uy, double* __restrict__ T)
@@ -685,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void d2q9_moments_kernel(long long n, doubl
     double drho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const double d = (double)Store<S>::to_real(pop[i * n + c]);
+        const double d = (double)Store<S>::to_real(pop[L.cell(i, c)]);
         drho += d;
         jx += cx9(i) * d;
         jy += cy9(i) * d;
@@ -697,29 +701,29 @@ __global__ __launch_bounds__(kBlock) void d2q9_moments_kernel(long long n, doubl
     if (T) T[c] = 1.0 / 3.0;
 }
 
-hipError_t launch_d2q9_init(int dtype, long long n, double rho0, const double* rho, const double* ux,
-                            const double* uy, void* pop, hipStream_t s)
+hipError_t launch_d2q9_init(int dtype, long long n, const PopLayout& L, double rho0, const double* rho,
+                            const double* ux, const double* uy, void* pop, hipStream_t s)
 {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     switch (dtype) {
-    case 0: d2q9_init_kernel<double><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (double*)pop); break;
-    case 1: d2q9_init_kernel<float><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (float*)pop); break;
-    case 2: d2q9_init_kernel<bf16_t><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (uint16_t*)pop); break;
-    case 3: d2q9_init_kernel<f16_t><<<grid, block, 0, s>>>(n, rho0, rho, ux, uy, (uint16_t*)pop); break;
+    case 0: d2q9_init_kernel<double><<<grid, block, 0, s>>>(n, L, rho0, rho, ux, uy, (double*)pop); break;
+    case 1: d2q9_init_kernel<float><<<grid, block, 0, s>>>(n, L, rho0, rho, ux, uy, (float*)pop); break;
+    case 2: d2q9_init_kernel<bf16_t><<<grid, block, 0, s>>>(n, L, rho0, rho, ux, uy, (uint16_t*)pop); break;
+    case 3: d2q9_init_kernel<f16_t><<<grid, block, 0, s>>>(n, L, rho0, rho, ux, uy, (uint16_t*)pop); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_d2q9_moments(int dtype, long long n, double rho0, const void* pop, double* rho,
-                               double* ux, double* uy, double* T, hipStream_t s)
+hipError_t launch_d2q9_moments(int dtype, long long n, const PopLayout& L, double rho0, const void* pop,
+                               double* rho, double* ux, double* uy, double* T, hipStream_t s)
 {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     switch (dtype) {
-    case 0: d2q9_moments_kernel<double><<<grid, block, 0, s>>>(n, rho0, (const double*)pop, rho, ux, uy, T); break;
-    case 1: d2q9_moments_kernel<float><<<grid, block, 0, s>>>(n, rho0, (const float*)pop, rho, ux, uy, T); break;
-    case 2: d2q9_moments_kernel<bf16_t><<<grid, block, 0, s>>>(n, rho0, (const uint16_t*)pop, rho, ux, uy, T); break;
-    case 3: d2q9_moments_kernel<f16_t><<<grid, block, 0, s>>>(n, rho0, (const uint16_t*)pop, rho, ux, uy, T); break;
+    case 0: d2q9_moments_kernel<double><<<grid, block, 0, s>>>(n, L, rho0, (const double*)pop, rho, ux, uy, T); break;
+    case 1: d2q9_moments_kernel<float><<<grid, block, 0, s>>>(n, L, rho0, (const float*)pop, rho, ux, uy, T); break;
+    case 2: d2q9_moments_kernel<bf16_t><<<grid, block, 0, s>>>(n, L, rho0, (const uint16_t*)pop, rho, ux, uy, T); break;
+    case 3: d2q9_moments_kernel<f16_t><<<grid, block, 0, s>>>(n, L, rho0, (const uint16_t*)pop, rho, ux, uy, T); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

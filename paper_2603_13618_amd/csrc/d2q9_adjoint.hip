@@ -52,7 +52,7 @@ __device__ __forceinline__ R shifted(const R* __restrict__ row, int x, int nx)
 }
 
 template <int SIGN, typename R>
-__device__ __forceinline__ void pull9(const R* __restrict__ f, long long plane, int x, int y, int nx,
+__device__ __forceinline__ void pull9(const R* __restrict__ f, const PopLayout& L, int x, int y, int nx,
                                       int ny, R (&out)[9])
 {
     sfor<9>([&](auto ic) {
@@ -60,7 +60,7 @@ __device__ __forceinline__ void pull9(const R* __restrict__ f, long long plane, 
         constexpr int cx = SIGN * acx(i), cy = SIGN * acy(i);
         int ys = y - cy;
         ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-        out[i] = shifted<cx>(f + i * plane + (long long)ys * nx, x, nx);
+        out[i] = shifted<cx>(f + L.at(i, ys, 0), x, nx);
     });
 }
 
@@ -82,7 +82,7 @@ __device__ __forceinline__ void cell_moments(const R (&d)[9], R rho0, R& drho, R
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void adj_seed_kernel(int nx, int ny, long long plane, R rho0,
+__global__ __launch_bounds__(kBlock) void adj_seed_kernel(int nx, int ny, long long plane, PopLayout L, R rho0,
                                                      const R* __restrict__ fprev,
                                                      R* __restrict__ lam)
 {
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void adj_seed_kernel(int nx, int ny, long l
     if (c >= plane) return;
     const int x = (int)(c % nx), y = (int)(c / nx);
     R d[9], drho, rho, ux, uy;
-    pull9<1>(fprev, plane, x, y, nx, ny, d);
+    pull9<1>(fprev, L, x, y, nx, ny, d);
     cell_moments(d, rho0, drho, rho, ux, uy);
     const R usq15 = R(1.5) * (ux * ux + uy * uy);
     // with x_i = f^neq_i / f^eq_i: g_i / f^eq_i = 1 + x_i, and the "1" part of
@@ -109,11 +109,11 @@ __global__ __launch_bounds__(kBlock) void adj_seed_kernel(int nx, int ny, long l
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j)
-        lam[j * plane + c] = lnr[j] - (bx * (R(acx(j)) - ux) + by * (R(acy(j)) - uy)) / rho;
+        lam[L.at(j, y, x)] = lnr[j] - (bx * (R(acx(j)) - ux) + by * (R(acy(j)) - uy)) / rho;
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void adj_step_kernel(int nx, int ny, long long plane, R rho0, R tau,
+__global__ __launch_bounds__(kBlock) void adj_step_kernel(int nx, int ny, long long plane, PopLayout L, R rho0, R tau,
                                                      const R* __restrict__ fprev,
                                                      const R* __restrict__ lam_in,
                                                      R* __restrict__ lam_out)
@@ -122,8 +122,8 @@ __global__ __launch_bounds__(kBlock) void adj_step_kernel(int nx, int ny, long l
     if (c >= plane) return;
     const int x = (int)(c % nx), y = (int)(c / nx);
     R d[9], l[9], drho, rho, ux, uy;
-    pull9<1>(fprev, plane, x, y, nx, ny, d);
-    pull9<-1>(lam_in, plane, x, y, nx, ny, l);
+    pull9<1>(fprev, L, x, y, nx, ny, d);
+    pull9<-1>(lam_in, L, x, y, nx, ny, l);
     cell_moments(d, rho0, drho, rho, ux, uy);
     const R usq = ux * ux + uy * uy;
     R a0 = R(0), bx = R(0), by = R(0);
@@ -139,12 +139,12 @@ __global__ __launch_bounds__(kBlock) void adj_step_kernel(int nx, int ny, long l
     const R it = R(1) / tau;
 #pragma unroll
     for (int j = 0; j < 9; ++j)
-        lam_out[j * plane + c] =
+        lam_out[L.at(j, y, x)] =
             (R(1) - it) * l[j] + it * (a0 + (bx * (R(acx(j)) - ux) + by * (R(acy(j)) - uy)) / rho);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void adj_init_kernel(int nx, int ny, long long plane,
+__global__ __launch_bounds__(kBlock) void adj_init_kernel(int nx, int ny, long long plane, PopLayout L,
                                                      const double* __restrict__ rho0,
                                                      const double* __restrict__ ux0,
                                                      const double* __restrict__ uy0,
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void adj_init_kernel(int nx, int ny, long l
     if (c >= plane) return;
     const int x = (int)(c % nx), y = (int)(c / nx);
     R l[9];
-    pull9<-1>(lam0, plane, x, y, nx, ny, l);
+    pull9<-1>(lam0, L, x, y, nx, ny, l);
     const double r = rho0[c], u = ux0[c], v = uy0[c];
     double gx = 0.0, gy = 0.0;
 #pragma unroll
@@ -178,10 +178,10 @@ hipError_t launch_adj_seed(int dtype, const D2Q9Args& a, const void* pop_prev, v
 {
     if (dtype == 0)
         adj_seed_kernel<double><<<cells_grid(a.plane), kBlock, 0, s>>>(
-            a.nx, a.ny, a.plane, a.rho0, (const double*)pop_prev, (double*)lam_out);
+            a.nx, a.ny, a.plane, a.L, a.rho0, (const double*)pop_prev, (double*)lam_out);
     else if (dtype == 1)
         adj_seed_kernel<float><<<cells_grid(a.plane), kBlock, 0, s>>>(
-            a.nx, a.ny, a.plane, (float)a.rho0, (const float*)pop_prev, (float*)lam_out);
+            a.nx, a.ny, a.plane, a.L, (float)a.rho0, (const float*)pop_prev, (float*)lam_out);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -192,11 +192,11 @@ hipError_t launch_adj_step(int dtype, const D2Q9Args& a, const void* pop_prev, c
 {
     if (dtype == 0)
         adj_step_kernel<double><<<cells_grid(a.plane), kBlock, 0, s>>>(
-            a.nx, a.ny, a.plane, a.rho0, a.tau, (const double*)pop_prev, (const double*)lam_in,
+            a.nx, a.ny, a.plane, a.L, a.rho0, a.tau, (const double*)pop_prev, (const double*)lam_in,
             (double*)lam_out);
     else if (dtype == 1)
         adj_step_kernel<float><<<cells_grid(a.plane), kBlock, 0, s>>>(
-            a.nx, a.ny, a.plane, (float)a.rho0, (float)a.tau, (const float*)pop_prev,
+            a.nx, a.ny, a.plane, a.L, (float)a.rho0, (float)a.tau, (const float*)pop_prev,
             (const float*)lam_in, (float*)lam_out);
     else
         return hipErrorInvalidValue;
@@ -209,10 +209,10 @@ hipError_t launch_adj_init(int dtype, const D2Q9Args& a, const double* rho0, con
 {
     if (dtype == 0)
         adj_init_kernel<double><<<cells_grid(a.plane), kBlock, 0, s>>>(
-            a.nx, a.ny, a.plane, rho0, ux0, uy0, (const double*)lam0, gux, guy);
+            a.nx, a.ny, a.plane, a.L, rho0, ux0, uy0, (const double*)lam0, gux, guy);
     else if (dtype == 1)
         adj_init_kernel<float><<<cells_grid(a.plane), kBlock, 0, s>>>(
-            a.nx, a.ny, a.plane, rho0, ux0, uy0, (const float*)lam0, gux, guy);
+            a.nx, a.ny, a.plane, a.L, rho0, ux0, uy0, (const float*)lam0, gux, guy);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -54,7 +54,14 @@ lks::GridShape d2q9_shape(const lks_config& c, int vec)
     g.vec = vec;
     g.tiles_x = (c.nx + kBlock * vec - 1) / (kBlock * vec);
     int rows = c.launch_rows;
-    if (rows <= 0) {
+    if (rows <= 0 && c.layout == LKS_LAYOUT_ROWS && store_bytes(c.dtype) >= 4) {
+        // row-interleaved FP32/FP64 state: two-row sweeps keep the workgroups
+        // in flight on a narrow band of grid rows, i.e. on a few contiguous
+        // stretches of HBM (FP32 at 4096^2 and 8192^2: 1 row 4-5 % slower,
+        // 4 rows 6 %, 16 rows 14-20 %).  16-bit storage spends relatively
+        // more time computing and keeps the long sweeps below.
+        rows = 2;
+    } else if (rows <= 0) {
         // at least ~1024 workgroups (4 per CU) with row sweeps of at most 16
         // rows: long enough to keep the next row in flight behind the
         // arithmetic, short enough to balance the CUs
@@ -88,7 +95,7 @@ const char* validate_config(const lks_config* c)
                                                       : all_ext & ~(unsigned)(LKS_X_COMP | LKS_X_STRAIN);
     if (c->ext_mask & ~valid_ext) return "ext_mask names a sensor this lattice does not have";
     if (c->model != LKS_MODEL_BGK && c->model != LKS_MODEL_DDF) return "model must be BGK or DDF";
-    if (c->model_reserved != 0) return "model_reserved must be 0";
+    if (c->layout != LKS_LAYOUT_PLANES && c->layout != LKS_LAYOUT_ROWS) return "layout must be PLANES or ROWS";
     if (c->model == LKS_MODEL_DDF) {
         if (c->lattice != LKS_D2Q25) return "the double distribution needs D2Q25";
         if (!(c->gamma > 1.0 && c->gamma < 2.0)) return "gamma must be in (1, 2)";
@@ -128,6 +135,7 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
     a.nx = c.nx;
     a.ny = c.ny;
     a.plane = (long long)c.nx * c.ny;
+    a.L = lks::pop_layout(c.layout, state_planes(c), c.nx, c.ny);
     a.bc_x = c.bc_x;
     a.bc_y = c.bc_y;
     a.mu = c.mu;
@@ -150,11 +158,18 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
     return a;
 }
 
-// workgroups of one step's cell kernel (the most any launch shape uses)
+// workgroups of one step's cell kernel: the most any vector width that
+// lks_create may pick uses (the automatic sweep length grows with the tile
+// count, so the narrowest vector does not always have the most workgroups)
 int step_blocks(const lks_config& c)
 {
     if (c.lattice == LKS_D2Q25) return d2q25_args(c).nblocks;
-    return d2q9_shape(c, 1).nblocks;   // the narrowest vector has the most workgroups
+    int nb = 0;
+    for (int vec : {1, 2, 4}) {
+        const int b = d2q9_shape(c, vec).nblocks;
+        nb = b > nb ? b : nb;
+    }
+    return nb;
 }
 
 // steps whose partial sums share the scratch before one reduction launch
@@ -187,6 +202,15 @@ size_t scratch_for(const lks_config& c) { return kHeader + partials_bytes(c) + a
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 } // namespace
+
+lks::PopLayout lks::pop_layout(int layout, int q, int nx, int ny)
+{
+    PopLayout L;
+    L.nx = nx;
+    L.pp = layout == LKS_LAYOUT_ROWS ? (long long)nx : (long long)nx * ny;
+    L.pr = layout == LKS_LAYOUT_ROWS ? (long long)q * nx : (long long)nx;
+    return L;
+}
 
 struct lks_ctx {
     lks_config cfg;
@@ -289,6 +313,7 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     a.nx = cfg->nx;
     a.ny = cfg->ny;
     a.plane = c->n;
+    a.L = lks::pop_layout(cfg->layout, c->Q, cfg->nx, cfg->ny);
     a.tau = cfg->tau;
     a.rho0 = cfg->rho0;
     std::memcpy(a.thr, cfg->thr, sizeof(a.thr));
@@ -302,6 +327,15 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     c->a25 = d2q25_args(*cfg);
     c->a25.aux = aux;
     c->nblocks = cfg->lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
+    // the partials area holds chunk_steps steps of the launch with the most
+    // workgroups; the launch chosen here may fit more steps per reduction
+    {
+        const long long per_step = (long long)c->nblocks * lks::kNsumsHost * (long long)sizeof(double);
+        long long k = (long long)partials_bytes(*cfg) / per_step;   // >= chunk_steps >= 1
+        if (k > kMaxChunk) k = kMaxChunk;
+        if (k > cfg->max_steps) k = cfg->max_steps;
+        c->chunk = (int)(k < 1 ? 1 : k);
+    }
     *out = c;
     return LKS_OK;
 }
@@ -313,12 +347,12 @@ lks_status lks_init_equilibrium(lks_ctx* c, const double* rho, const double* ux,
     if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
     if (c->cfg.lattice == LKS_D2Q25 && !T) return fail(c, LKS_EINVAL, "T is required on D2Q25");
     hipError_t e = ddf(c->cfg)
-                       ? lks::launch_d2q25_ddf_init(c->cfg.dtype, c->n, c->cfg.rho0, cv_of(c->cfg), rho,
-                                                    ux, uy, T, c->buf.pop[0], c->stream)
+                       ? lks::launch_d2q25_ddf_init(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0, cv_of(c->cfg),
+                                                    rho, ux, uy, T, c->buf.pop[0], c->stream)
                    : c->cfg.lattice == LKS_D2Q25
-                       ? lks::launch_d2q25_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy, T,
+                       ? lks::launch_d2q25_init(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0, rho, ux, uy, T,
                                                 c->buf.pop[0], c->stream)
-                       : lks::launch_d2q9_init(c->cfg.dtype, c->n, c->cfg.rho0, rho, ux, uy,
+                       : lks::launch_d2q9_init(c->cfg.dtype, c->n, c->a9.L, c->cfg.rho0, rho, ux, uy,
                                                c->buf.pop[0], c->stream);
     if (lks_status s = hip_check(c, e, "init kernel")) return s;
     if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
@@ -407,12 +441,13 @@ lks_status lks_moments(lks_ctx* c, double* rho, double* ux, double* uy, double* 
     if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
     if (!c->ready) return fail(c, LKS_ESTATE, "moments before init_equilibrium or restore");
     hipError_t e = ddf(c->cfg)
-                       ? lks::launch_d2q25_ddf_moments(c->cfg.dtype, c->n, c->cfg.rho0, cv_of(c->cfg),
-                                                       c->buf.pop[c->cur], rho, ux, uy, T, c->stream)
+                       ? lks::launch_d2q25_ddf_moments(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0,
+                                                       cv_of(c->cfg), c->buf.pop[c->cur], rho, ux, uy, T,
+                                                       c->stream)
                    : c->cfg.lattice == LKS_D2Q25
-                       ? lks::launch_d2q25_moments(c->cfg.dtype, c->n, c->cfg.rho0,
+                       ? lks::launch_d2q25_moments(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0,
                                                    c->buf.pop[c->cur], rho, ux, uy, T, c->stream)
-                       : lks::launch_d2q9_moments(c->cfg.dtype, c->n, c->cfg.rho0,
+                       : lks::launch_d2q9_moments(c->cfg.dtype, c->n, c->a9.L, c->cfg.rho0,
                                                   c->buf.pop[c->cur], rho, ux, uy, T, c->stream);
     return hip_check(c, e, "moments kernel");
 }

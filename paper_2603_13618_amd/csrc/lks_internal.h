@@ -31,9 +31,27 @@ struct ExtArgs {
     float thr_f[kNumExtHost][2];     // the same rounded to FP32
 };
 
+// Where population i of cell (x, y) lives in a state buffer: element
+// i * pp + y * pr + x.  Plane-major [Q][ny][nx]: pp = nx * ny, pr = nx;
+// row-interleaved [ny][Q][nx]: pp = nx, pr = Q * nx.  Sensors, flags and
+// fields are always plane-major.
+struct PopLayout {
+    int nx;
+    long long pp, pr;
+    __host__ __device__ long long at(int i, int y, int x) const { return i * pp + y * pr + x; }
+    // population i of cell c = y * nx + x
+    __host__ __device__ long long cell(int i, long long c) const
+    {
+        const long long y = c / nx;
+        return i * pp + y * pr + (c - y * nx);
+    }
+};
+PopLayout pop_layout(int layout, int q, int nx, int ny);
+
 struct D2Q9Args {
     int nx, ny;
-    long long plane;          // nx * ny
+    long long plane;          // nx * ny (sensor planes)
+    PopLayout L;              // population planes
     double tau;
     double rho0;
     double thr[4][2];
@@ -48,7 +66,8 @@ struct D2Q9Args {
 
 struct D2Q25Args {
     int nx, ny;
-    long long plane;
+    long long plane;          // nx * ny (sensor planes, hand-over planes)
+    PopLayout L;              // population planes
     int bc_x, bc_y;           // 0 periodic, 1 outflow
     double mu, dt, dx;
     double rho0;
@@ -84,24 +103,25 @@ hipError_t launch_d2q25(int dtype, const D2Q25Args& a, const void* fin, void* fo
 void d2q25_tile_shape(int dtype, int model, int* tx, int* ty);
 
 // equilibrium initial states from FP64 fields [ny][nx] (n = nx*ny cells)
-hipError_t launch_d2q9_init(int dtype, long long n, double rho0, const double* rho,
+hipError_t launch_d2q9_init(int dtype, long long n, const PopLayout& L, double rho0, const double* rho,
                             const double* ux, const double* uy, void* pop, hipStream_t s);
-hipError_t launch_d2q25_init(int dtype, long long n, double rho0, const double* rho,
+hipError_t launch_d2q25_init(int dtype, long long n, const PopLayout& L, double rho0, const double* rho,
                              const double* ux, const double* uy, const double* T, void* pop,
                              hipStream_t s);
 
 // FP64 moments of a stored state (T may be null)
-hipError_t launch_d2q9_moments(int dtype, long long n, double rho0, const void* pop, double* rho,
-                               double* ux, double* uy, double* T, hipStream_t s);
-hipError_t launch_d2q25_moments(int dtype, long long n, double rho0, const void* pop,
+hipError_t launch_d2q9_moments(int dtype, long long n, const PopLayout& L, double rho0, const void* pop,
+                               double* rho, double* ux, double* uy, double* T, hipStream_t s);
+hipError_t launch_d2q25_moments(int dtype, long long n, const PopLayout& L, double rho0, const void* pop,
                                 double* rho, double* ux, double* uy, double* T, hipStream_t s);
-// double distribution: pop holds [50][n] (f deviations, then g deviations
-// from (C_v - 1) w_i rho0)
-hipError_t launch_d2q25_ddf_init(int dtype, long long n, double rho0, double cv, const double* rho,
-                                 const double* ux, const double* uy, const double* T, void* pop,
-                                 hipStream_t s);
-hipError_t launch_d2q25_ddf_moments(int dtype, long long n, double rho0, double cv, const void* pop,
-                                    double* rho, double* ux, double* uy, double* T, hipStream_t s);
+// double distribution: 50 populations per cell (f deviations, then g
+// deviations from (C_v - 1) w_i rho0)
+hipError_t launch_d2q25_ddf_init(int dtype, long long n, const PopLayout& L, double rho0, double cv,
+                                 const double* rho, const double* ux, const double* uy, const double* T,
+                                 void* pop, hipStream_t s);
+hipError_t launch_d2q25_ddf_moments(int dtype, long long n, const PopLayout& L, double rho0, double cv,
+                                    const void* pop, double* rho, double* ux, double* uy, double* T,
+                                    hipStream_t s);
 
 // Reduce partials[step][nblocks][8] of nsteps steps into sums rows
 // (row0 + step) mod max_rows; adds the reference mass/energy n_cells*rho0*(1, e_ref).

@@ -21,6 +21,8 @@ PERIODIC, OUTFLOW = 0, 1
 S_KL, S_NEQ, S_PI, S_Q, S_QE = 1, 2, 4, 8, 16
 MODEL_BGK, MODEL_DDF = 0, 1
 MODELS = {"bgk": MODEL_BGK, "ddf": MODEL_DDF}
+LAYOUT_PLANES, LAYOUT_ROWS = 0, 1
+LAYOUTS = {"planes": LAYOUT_PLANES, "rows": LAYOUT_ROWS}
 NSUMS = 8
 # extension sensors (bit k of ext_mask; flag_mask bit 8 + k), plane order
 EXT_NAMES = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf", "comp", "strain")
@@ -64,7 +66,7 @@ class Config(ctypes.Structure):
                 ("thr", (ctypes.c_double * 2) * 4), ("max_steps", ctypes.c_int32),
                 ("launch_vec", ctypes.c_int32), ("ext_mask", ctypes.c_uint32),
                 ("ext_reserved", ctypes.c_int32), ("thr_ext", (ctypes.c_double * 2) * MAX_EXT),
-                ("model", ctypes.c_int32), ("model_reserved", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("thr_qe", ctypes.c_double * 2)]
 
@@ -144,7 +146,7 @@ def _stream_handle(device):
 def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                 bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
                 launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
-                prandtl=0.71, thr_qe=None):
+                prandtl=0.71, thr_qe=None, layout=LAYOUT_PLANES):
     c = Config()
     c.lattice, c.nx, c.ny = lattice, nx, ny
     c.dtype = DTYPES[dtype] if isinstance(dtype, str) else dtype
@@ -164,7 +166,7 @@ def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, 
     for k in range(MAX_EXT):
         c.thr_ext[k][0], c.thr_ext[k][1] = float(te[k, 0]), float(te[k, 1])
     c.model = MODELS[model] if isinstance(model, str) else model
-    c.model_reserved = 0
+    c.layout = LAYOUTS[layout] if isinstance(layout, str) else layout
     c.gamma, c.prandtl = gamma, prandtl
     tq = (math.inf, math.inf) if thr_qe is None else tuple(float(v) for v in thr_qe)
     c.thr_qe[0], c.thr_qe[1] = tq
@@ -184,7 +186,10 @@ def _check(status, ctx=None):
 class Lattice:
     """One simulation context with torch-owned device buffers.
 
-    Attributes: pop (2 tensors [Q, ny, nx]), sensors [nsens, ny, nx] (the
+    Attributes: pop (2 tensors [Q, ny, nx]: views of the state buffers, which
+    are [ny, Q, nx] with layout "rows" (default; the faster one for D2Q9
+    FP32/FP64 storage and never slower) and [Q, ny, nx] with layout "planes";
+    new_state() makes another), sensors [nsens, ny, nx] (the
     base sensors, then one plane per extension sensor in ext, in EXT_NAMES
     order), flags [ny, nx] uint8, sums [max_steps, 8] float64.
     ext: extension sensors (names from EXT_NAMES, indices or a bit mask);
@@ -199,11 +204,12 @@ class Lattice:
     def __init__(self, lattice=D2Q9, nx=64, ny=64, dtype="f32", tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                  bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
                  launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
-                 prandtl=0.71, thr_qe=None, device="cuda"):
+                 prandtl=0.71, thr_qe=None, layout=LAYOUT_ROWS, device="cuda"):
         self.device = torch.device(device)
         self.cfg = make_config(lattice, nx, ny, dtype, tau, mu, dt, dx, bc, rho0, thr, flag_mask,
                                max_steps, launch_rows, launch_vec, ext, thr_ext, model, gamma,
-                               prandtl, thr_qe)
+                               prandtl, thr_qe, layout)
+        self.layout = self.cfg.layout
         self.model = self.cfg.model
         self.Q = 50 if self.model == MODEL_DDF else lattice
         self.nx, self.ny = nx, ny
@@ -214,7 +220,7 @@ class Lattice:
         sdt = torch.float64 if self.dtype == F64 else torch.float32
         tdt = _TORCH_STORE[self.dtype]
         dev = self.device
-        self.pop = [torch.zeros((self.Q, ny, nx), dtype=tdt, device=dev) for _ in range(2)]
+        self.pop = [self._alloc_state(tdt, dev, torch.zeros) for _ in range(2)]
         self.sensors = torch.zeros((nsens, ny, nx), dtype=sdt, device=dev)
         self.flags = torch.zeros((ny, nx), dtype=torch.uint8, device=dev)
         self.sums = torch.zeros((max_steps, NSUMS), dtype=torch.float64, device=dev)
@@ -234,6 +240,24 @@ class Lattice:
         st = lib().lks_create(ctypes.byref(self.cfg), ctypes.byref(self.buf),
                               _stream_handle(dev), ctypes.byref(self.ctx))
         _check(st, None)
+
+    def _alloc_state(self, tdt, dev, make=torch.empty):
+        if self.layout == LAYOUT_ROWS:
+            return make((self.ny, self.Q, self.nx), dtype=tdt, device=dev).permute(1, 0, 2)
+        return make((self.Q, self.ny, self.nx), dtype=tdt, device=dev)
+
+    def new_state(self):
+        """An uninitialised state tensor [Q, ny, nx] in this context's layout."""
+        return self._alloc_state(self.pop[0].dtype, self.device)
+
+    def _state_arg(self, t, what):
+        ok = (tuple(t.shape) == tuple(self.pop[0].shape) and t.dtype == self.pop[0].dtype
+              and t.device == self.pop[0].device and t.stride() == self.pop[0].stride()
+              and t.storage_offset() == 0)
+        if not ok:
+            raise ValueError(f"{what} must be a [Q, ny, nx] {self.pop[0].dtype} state in this "
+                             f"context's layout (strides {self.pop[0].stride()}): use new_state()")
+        return _ptr(t)
 
     def macro_sensors(self, rho, ux, uy, T=None, mu=0.0, lam=0.0, kappa=0.0, per_rho=False,
                       which=MACRO_NAMES, out=None):
@@ -302,7 +326,8 @@ class Lattice:
 
     def step_from(self, src, dst):
         """One fused step from the state tensor src into dst (step count unchanged)."""
-        _check(lib().lks_step_from(self.ctx, _ptr(src), _ptr(dst)), self.ctx)
+        _check(lib().lks_step_from(self.ctx, self._state_arg(src, "src"),
+                                   self._state_arg(dst, "dst")), self.ctx)
 
     def current(self):
         i, n = ctypes.c_int32(), ctypes.c_int64()
@@ -331,25 +356,30 @@ class Lattice:
     def read_host(self, what):
         """Synchronous copy to a numpy array through lks_read_host (what 0..3)."""
         src = [self.state, self.sensors, self.flags, self.sums][what]
+        rows = what == 0 and self.layout == LAYOUT_ROWS
+        shape = (self.ny, self.Q, self.nx) if rows else tuple(src.shape)
         if src.dtype == torch.bfloat16:
-            out = np.empty(src.shape, np.uint16)
+            out = np.empty(shape, np.uint16)
         else:
-            out = np.empty(src.shape, {torch.float64: np.float64, torch.float32: np.float32,
-                                       torch.float16: np.float16, torch.uint8: np.uint8}[src.dtype])
+            out = np.empty(shape, {torch.float64: np.float64, torch.float32: np.float32,
+                                   torch.float16: np.float16, torch.uint8: np.uint8}[src.dtype])
         _check(lib().lks_read_host(self.ctx, what, out.ctypes.data_as(ctypes.c_void_p),
                                    out.nbytes), self.ctx)
-        return out
+        return out.transpose(1, 0, 2) if rows else out
 
     # ---- adjoint (D2Q9) ----
     def adjoint_seed_kl(self, pop_prev, lam_out):
-        _check(lib().lks_adjoint_seed_kl(self.ctx, _ptr(pop_prev), _ptr(lam_out)), self.ctx)
+        _check(lib().lks_adjoint_seed_kl(self.ctx, self._state_arg(pop_prev, "pop_prev"),
+                                         self._state_arg(lam_out, "lam_out")), self.ctx)
 
     def adjoint_step(self, pop_prev, lam_in, lam_out):
-        _check(lib().lks_adjoint_step(self.ctx, _ptr(pop_prev), _ptr(lam_in), _ptr(lam_out)),
-               self.ctx)
+        _check(lib().lks_adjoint_step(self.ctx, self._state_arg(pop_prev, "pop_prev"),
+                                      self._state_arg(lam_in, "lam_in"),
+                                      self._state_arg(lam_out, "lam_out")), self.ctx)
 
     def adjoint_init(self, rho0, ux0, uy0, lam0, gux, guy):
-        _check(lib().lks_adjoint_init(self.ctx, _ptr(rho0), _ptr(ux0), _ptr(uy0), _ptr(lam0),
+        _check(lib().lks_adjoint_init(self.ctx, _ptr(rho0), _ptr(ux0), _ptr(uy0),
+                                      self._state_arg(lam0, "lam0"),
                                       _ptr(gux), _ptr(guy)), self.ctx)
 
 

@@ -58,13 +58,14 @@ def test_abi_struct_layout_matches_header(tmp_path):
     # of include/lks.h
     fields = ["lattice", "nx", "dtype", "tau", "rho0", "flag_mask", "launch_rows", "thr",
               "max_steps", "launch_vec", "ext_mask", "ext_reserved", "thr_ext", "model",
-              "model_reserved", "gamma", "prandtl", "thr_qe"]
+              "layout", "gamma", "prandtl", "thr_qe"]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lks.h\"\nint main(void){\n"
                    + 'printf("%zu %zu", sizeof(lks_config), sizeof(lks_buffers));\n'
                    + "".join(f'printf(" %zu", offsetof(lks_config, {f}));\n' for f in fields)
                    + 'printf(" %zu %zu", offsetof(lks_buffers, sensors), offsetof(lks_buffers, scratch_bytes));'
-                   + 'printf(" %zu %zu %zu\\n", sizeof(lks_transport), offsetof(lks_transport, kappa), offsetof(lks_transport, per_rho));'
+                   + 'printf(" %zu %zu %zu", sizeof(lks_transport), offsetof(lks_transport, kappa), offsetof(lks_transport, per_rho));'
+                   + 'printf(" %d %d %d %d\\n", LKS_LAYOUT_PLANES, LKS_LAYOUT_ROWS, LKS_MODEL_BGK, LKS_MODEL_DDF);'
                    + "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
@@ -75,6 +76,7 @@ def test_abi_struct_layout_matches_header(tmp_path):
     want += [getattr(lks.Config, f).offset for f in fields]
     want += [lks.Buffers.sensors.offset, lks.Buffers.scratch_bytes.offset]
     want += [ctypes.sizeof(lks.Transport), lks.Transport.kappa.offset, lks.Transport.per_rho.offset]
+    want += [lks.LAYOUT_PLANES, lks.LAYOUT_ROWS, lks.MODEL_BGK, lks.MODEL_DDF]
     assert got == want
 
 
@@ -117,9 +119,25 @@ def test_double_distribution_validation_on_host():
            lks.make_config(25, 64, 64, "f32", mu=1e-3, dt=1e-3, dx=0.1, model=2)]
     for c in bad:
         assert lks.scratch_bytes(c) == 0 and L.lks_sensor_planes(ctypes.byref(c)) == 0
-    r = lks.make_config(25, 64, 64, "f32", **kw)
-    r.model_reserved = 1
-    assert lks.scratch_bytes(r) == 0
+
+
+def test_population_layout_validation_on_host():
+    L = lks.lib()
+    q25 = dict(mu=1e-3, dt=1e-3, dx=0.1)
+    for lat, kw in ((9, dict(tau=0.6)), (25, q25), (25, dict(q25, model="ddf"))):
+        planes = lks.make_config(lat, 64, 48, "f32", **kw)
+        rows = lks.make_config(lat, 64, 48, "f32", layout="rows", **kw)
+        assert rows.layout == lks.LAYOUT_ROWS and planes.layout == lks.LAYOUT_PLANES
+        # the layout moves values, not bytes: same sensor planes; scratch
+        # follows the launch shape, which on D2Q9 depends on the layout
+        assert lks.scratch_bytes(rows) > 0 and lks.scratch_bytes(planes) > 0
+        if lat == 25:
+            assert lks.scratch_bytes(rows) == lks.scratch_bytes(planes)
+        assert L.lks_sensor_planes(ctypes.byref(rows)) == L.lks_sensor_planes(ctypes.byref(planes))
+        for v in (2, -1):
+            r = lks.make_config(lat, 64, 48, "f32", **kw)
+            r.layout = v
+            assert lks.scratch_bytes(r) == 0
 
 
 @pytest.mark.parametrize("name", ["lks_step", "lks_moments", "lks_check", "lks_init_equilibrium"])

@@ -186,6 +186,12 @@ typedef struct {
     double gamma;         /* LKS_MODEL_DDF: adiabatic exponent, 1 < gamma < 2  */
     double prandtl;       /* LKS_MODEL_DDF: Prandtl number, 0 < Pr <= 1        */
     double thr_qe[2];     /* LKS_MODEL_DDF: (theta1 <= theta2) of S_QE         */
+    int32_t launch_nt;    /* stores of the fused D2Q9 step: 0 picks (the
+                             non-temporal hint when the two state buffers
+                             exceed the 256 MB last-level cache), 1 plain,
+                             2 non-temporal (a launch hint only: results are
+                             identical)                                        */
+    int32_t launch_reserved; /* must be 0                                       */
 } lks_config;
 
 typedef struct {

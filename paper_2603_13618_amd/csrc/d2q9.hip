@@ -377,7 +377,10 @@ template <typename S, int VEC> struct StageGeom {
     static constexpr int PE = ok ? PE0 : 1;           // elements per piece
 };
 
-template <typename S, int VEC, bool EXT = false>
+// NT: stores with the non-temporal hint (the launcher sets it when the two
+// state buffers exceed the last-level cache, so the next step's loads come
+// from HBM anyway)
+template <typename S, int VEC, bool EXT = false, bool NT = false>
 __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags,
@@ -471,15 +474,15 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             const long long off = (long long)y * nx + x0;
             const long long poff = a.L.at(0, y, x0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) store_vec<S, VEC>(fout + i * a.L.pp + poff, res[i]);
-            store_pack<R, VEC>(sens + off, s_kl);
-            store_pack<R, VEC>(sens + plane + off, s_neq);
-            store_pack<R, VEC>(sens + 2 * plane + off, s_pi);
-            store_pack<uint8_t, VEC>(flags + off, fl);
+            for (int i = 0; i < 9; ++i) store_vec<S, VEC, NT>(fout + i * a.L.pp + poff, res[i]);
+            store_pack<R, VEC, NT>(sens + off, s_kl);
+            store_pack<R, VEC, NT>(sens + plane + off, s_neq);
+            store_pack<R, VEC, NT>(sens + 2 * plane + off, s_pi);
+            store_pack<uint8_t, VEC, NT>(flags + off, fl);
             if constexpr (EXT) {
 #pragma unroll
                 for (int q = 0; q < kNumExt; ++q)
-                    if (a.x.plane[q] >= 0) store_pack<R, VEC>(sens + a.x.plane[q] * plane + off, xres[q]);
+                    if (a.x.plane[q] >= 0) store_pack<R, VEC, NT>(sens + a.x.plane[q] * plane + off, xres[q]);
             }
         }
     };
@@ -609,7 +612,9 @@ static hipError_t launch_pass(int pass, const D2Q9Args& a, const void* fin, void
             } else {
                 return hipErrorInvalidValue;
             }
-        } else if (LKS_D2Q9_LDS_STAGE && StageGeom<S, VEC>::ok)
+        } else if (LKS_D2Q9_LDS_STAGE && StageGeom<S, VEC>::ok && a.nt_stores)
+            d2q9_fused_lds<S, VEC, false, true><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
+        else if (LKS_D2Q9_LDS_STAGE && StageGeom<S, VEC>::ok)
             d2q9_fused_lds<S, VEC><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);
         else
             d2q9_kernel<S, VEC, kFused><<<grid, block, 0, st>>>(a, in, out, sv, flags, partials, faults);

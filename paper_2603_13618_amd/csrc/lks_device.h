@@ -18,11 +18,6 @@
 #define LKS_CELL_KERNEL_ATTR
 #endif
 
-// Non-temporal (streaming) stores for outputs that are not re-read by the
-// same step: 1 = use them.
-#ifndef LKS_NT_STORES
-#define LKS_NT_STORES 0
-#endif
 // Rows of populations the D2Q9 kernel keeps in flight ahead of the row it
 // computes.
 #ifndef LKS_D2Q9_PREFETCH
@@ -113,13 +108,15 @@ template <> struct Store<f16_t> {
 // VEC consecutive elements as one aligned memory operation
 template <typename T, int VEC> struct alignas(sizeof(T) * VEC) Pack { T v[VEC]; };
 
-// store of a pack, optionally with the non-temporal hint
-template <typename T, int VEC>
+// store of a pack, with the non-temporal hint when NT (for outputs that no
+// cache can hold until they are read again)
+template <typename T, int VEC, bool NT = false>
 __device__ __forceinline__ void store_raw_pack(T* __restrict__ p, const Pack<T, VEC>& pk)
 {
-#if LKS_NT_STORES
     constexpr int bytes = (int)sizeof(T) * VEC;
-    if constexpr (bytes == 16) {
+    if constexpr (!NT) {
+        *reinterpret_cast<Pack<T, VEC>*>(p) = pk;
+    } else if constexpr (bytes == 16) {
         using V = __attribute__((ext_vector_type(4))) unsigned int;
         __builtin_nontemporal_store(__builtin_bit_cast(V, pk), reinterpret_cast<V*>(p));
     } else if constexpr (bytes == 8) {
@@ -132,9 +129,6 @@ __device__ __forceinline__ void store_raw_pack(T* __restrict__ p, const Pack<T, 
     } else {
         __builtin_nontemporal_store(__builtin_bit_cast(unsigned char, pk), reinterpret_cast<unsigned char*>(p));
     }
-#else
-    *reinterpret_cast<Pack<T, VEC>*>(p) = pk;
-#endif
 }
 
 template <typename S, int VEC>
@@ -161,7 +155,7 @@ __device__ __forceinline__ void load_vec(const typename Store<S>::raw* __restric
     for (int k = 0; k < VEC; ++k) out[k] = Store<S>::to_real(pk.v[k]);
 }
 
-template <typename S, int VEC>
+template <typename S, int VEC, bool NT = false>
 __device__ __forceinline__ void store_vec(typename Store<S>::raw* __restrict__ p,
                                           const typename Store<S>::real (&in)[VEC])
 {
@@ -184,16 +178,16 @@ __device__ __forceinline__ void store_vec(typename Store<S>::raw* __restrict__ p
 #pragma unroll
         for (int k = 0; k < VEC; ++k) pk.v[k] = Store<S>::from_real(in[k]);
     }
-    store_raw_pack(p, pk);
+    store_raw_pack<raw, VEC, NT>(p, pk);
 }
 
-template <typename T, int VEC>
+template <typename T, int VEC, bool NT = false>
 __device__ __forceinline__ void store_pack(T* __restrict__ p, const T (&in)[VEC])
 {
     Pack<T, VEC> pk;
 #pragma unroll
     for (int k = 0; k < VEC; ++k) pk.v[k] = in[k];
-    store_raw_pack(p, pk);
+    store_raw_pack<T, VEC, NT>(p, pk);
 }
 
 // ---------------------------------------------------------------------------

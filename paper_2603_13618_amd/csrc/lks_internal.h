@@ -62,6 +62,7 @@ struct D2Q9Args {
     float inv_tau_f, rho0_f;
     float thr_f[4][2];
     ExtArgs x;
+    int nt_stores;            // fused step: non-temporal stores (large states)
 };
 
 struct D2Q25Args {

@@ -68,7 +68,8 @@ class Config(ctypes.Structure):
                 ("ext_reserved", ctypes.c_int32), ("thr_ext", (ctypes.c_double * 2) * MAX_EXT),
                 ("model", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("thr_qe", ctypes.c_double * 2)]
+                ("thr_qe", ctypes.c_double * 2), ("launch_nt", ctypes.c_int32),
+                ("launch_reserved", ctypes.c_int32)]
 
 
 class Box(ctypes.Structure):
@@ -146,7 +147,7 @@ def _stream_handle(device):
 def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                 bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
                 launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
-                prandtl=0.71, thr_qe=None, layout=LAYOUT_PLANES):
+                prandtl=0.71, thr_qe=None, layout=LAYOUT_PLANES, launch_nt=0):
     c = Config()
     c.lattice, c.nx, c.ny = lattice, nx, ny
     c.dtype = DTYPES[dtype] if isinstance(dtype, str) else dtype
@@ -167,6 +168,7 @@ def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, 
         c.thr_ext[k][0], c.thr_ext[k][1] = float(te[k, 0]), float(te[k, 1])
     c.model = MODELS[model] if isinstance(model, str) else model
     c.layout = LAYOUTS[layout] if isinstance(layout, str) else layout
+    c.launch_nt, c.launch_reserved = launch_nt, 0
     c.gamma, c.prandtl = gamma, prandtl
     tq = (math.inf, math.inf) if thr_qe is None else tuple(float(v) for v in thr_qe)
     c.thr_qe[0], c.thr_qe[1] = tq
@@ -204,11 +206,11 @@ class Lattice:
     def __init__(self, lattice=D2Q9, nx=64, ny=64, dtype="f32", tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                  bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
                  launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
-                 prandtl=0.71, thr_qe=None, layout=LAYOUT_ROWS, device="cuda"):
+                 prandtl=0.71, thr_qe=None, layout=LAYOUT_ROWS, launch_nt=0, device="cuda"):
         self.device = torch.device(device)
         self.cfg = make_config(lattice, nx, ny, dtype, tau, mu, dt, dx, bc, rho0, thr, flag_mask,
                                max_steps, launch_rows, launch_vec, ext, thr_ext, model, gamma,
-                               prandtl, thr_qe, layout)
+                               prandtl, thr_qe, layout, launch_nt)
         self.layout = self.cfg.layout
         self.model = self.cfg.model
         self.Q = 50 if self.model == MODEL_DDF else lattice

@@ -58,7 +58,7 @@ def test_abi_struct_layout_matches_header(tmp_path):
     # of include/lks.h
     fields = ["lattice", "nx", "dtype", "tau", "rho0", "flag_mask", "launch_rows", "thr",
               "max_steps", "launch_vec", "ext_mask", "ext_reserved", "thr_ext", "model",
-              "layout", "gamma", "prandtl", "thr_qe"]
+              "layout", "gamma", "prandtl", "thr_qe", "launch_nt", "launch_reserved"]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lks.h\"\nint main(void){\n"
                    + 'printf("%zu %zu", sizeof(lks_config), sizeof(lks_buffers));\n'
@@ -138,6 +138,13 @@ def test_population_layout_validation_on_host():
             r = lks.make_config(lat, 64, 48, "f32", **kw)
             r.layout = v
             assert lks.scratch_bytes(r) == 0
+    # the store hint: 0 automatic, 1 plain, 2 non-temporal; nothing else
+    for v in (0, 1, 2):
+        assert lks.scratch_bytes(lks.make_config(9, 64, 48, "f32", tau=0.6, launch_nt=v)) > 0
+    for field, v in (("launch_nt", 3), ("launch_nt", -1), ("launch_reserved", 1)):
+        r = lks.make_config(9, 64, 48, "f32", tau=0.6)
+        setattr(r, field, v)
+        assert lks.scratch_bytes(r) == 0
 
 
 @pytest.mark.parametrize("name", ["lks_step", "lks_moments", "lks_check", "lks_init_equilibrium"])

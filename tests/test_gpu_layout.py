@@ -255,3 +255,26 @@ def test_partial_sums_stay_inside_scratch(layout):
         _same(sums, ref.sums, "sums")
     finally:
         L.lks_destroy(ctx)
+
+
+@pytest.mark.parametrize("dtype,vec,layout", [("f32", 0, "rows"), ("f32", 1, "rows"), ("f64", 0, "rows"),
+                                              ("bf16", 0, "rows"), ("f32", 0, "planes")])
+def test_d2q9_store_hint_bit_identical(dtype, vec, layout):
+    # plain and non-temporal stores of the fused step (the hint the library
+    # picks by state size) write the same bytes
+    nx, ny, steps = 200, 72, 12
+    rho, ux, uy = inputs.random_state((ny, nx), seed=12, umax=0.05)
+    thr = np.array([[1e-6, 1e-5], [1e-3, 1e-2], [1e-3, 1e-2], [np.inf, np.inf]])
+    out = []
+    for nt in (1, 2):
+        lat = lks.Lattice(9, nx, ny, dtype, tau=0.6, thr=thr, flag_mask=7, max_steps=steps,
+                          launch_vec=vec, layout=layout, launch_nt=nt)
+        lat.init(rho, ux, uy)
+        lat.step(steps)
+        out.append(lat)
+    torch.cuda.synchronize()
+    a, b = out
+    _same(a.state, b.state, "state")
+    _same(a.sensors, b.sensors, "sensors")
+    _same(a.flags, b.flags, "flags")
+    _same(a.sums, b.sums, "sums")

@@ -38,7 +38,11 @@ FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 # sensors + 1 flag per cell (the method's bytes; the two kernels of the step
 # also hand 6 values per cell over and read g's own cell twice: 569 B)
 BYTES_F32_DDF = 421
-DDF_KERNEL = "d2q25_ddf_kernel<float,16,8,false> + d2q25_ddf_g_kernel<float,16,8>"
+DDF_KERNEL = "d2q25_ddf_kernel<float,16,8,false> + d2q25_ddf_g_kernel<float,32,8>"
+# the single-distribution D2Q25 step (FP32): 25 x 4 read + 25 x 4 written + 4 x 4
+# sensors + 1 flag per cell
+BYTES_F32_Q25 = 217
+Q25_KERNEL = "d2q25_kernel<float,32,8,false>"
 LAYOUT = "rows"                 # population layout of every lattice (--layout)
 
 
@@ -55,6 +59,8 @@ def parse():
                    help="also time the fused steps with every extension sensor on")
     p.add_argument("--ddf", action="store_true",
                    help="also time the D2Q25 double-distribution step on the 2048^2 Riemann problem")
+    p.add_argument("--q25", action="store_true",
+                   help="also time the D2Q25 single-distribution step on the 2048^2 Riemann problem")
     p.add_argument("--regrid", action="store_true",
                    help="also time the regridding hand-off on the final flag map")
     p.add_argument("--layout", choices=["planes", "rows"], default="rows",
@@ -299,6 +305,8 @@ def main():
         out["ext"] = time_ext(torch, lks, inputs, workloads, dev, ev)
     if args.ddf:
         out["ddf"] = time_ddf(torch, lks, inputs, workloads, dev, ev)
+    if args.q25:
+        out["q25"] = time_q25(torch, lks, inputs, workloads, dev, ev)
     if regrid is not None:
         out["regrid"] = regrid
 
@@ -432,11 +440,35 @@ def ddf_lattice(lks, inputs, workloads, dev, steps, ext=None):
     return lat
 
 
+def q25_lattice(lks, inputs, workloads, dev, steps):
+    """The single-distribution D2Q25 Riemann workload, initialised (FP32)."""
+    wl = workloads.RIEMANN_2048
+    n = wl["nx"]
+    rho, ux, uy, T, states = inputs.riemann_quadrants(n, seed=wl["seed"])
+    dx = 1.0 / n
+    lat = lks.Lattice(25, n, n, "f32", mu=wl["mu"], dt=inputs.riemann_dt(states, dx), dx=dx,
+                      bc=(1, 1), thr=wl["thr"], flag_mask=wl["flag_mask"], max_steps=max(steps, 1),
+                      layout=LAYOUT, device=dev)
+    lat.init(rho, ux, uy, T)
+    return lat
+
+
 def time_ddf(torch, lks, inputs, workloads, dev, ev):
-    """Fused double-distribution steps (timing only): whole steps, then the
-    step kernel alone between the two state buffers."""
+    """Fused double-distribution steps (timing only)."""
     k = 40
-    lat = ddf_lattice(lks, inputs, workloads, dev, k)
+    return time_d2q25(torch, ev, ddf_lattice(lks, inputs, workloads, dev, k), k,
+                      workloads.RIEMANN_2048_DDF["name"], DDF_KERNEL, BYTES_F32_DDF)
+
+
+def time_q25(torch, lks, inputs, workloads, dev, ev):
+    """Fused single-distribution D2Q25 steps (timing only)."""
+    k = 40
+    return time_d2q25(torch, ev, q25_lattice(lks, inputs, workloads, dev, k), k,
+                      workloads.RIEMANN_2048["name"], Q25_KERNEL, BYTES_F32_Q25)
+
+
+def time_d2q25(torch, ev, lat, k, name, kernel, bpl):
+    """Whole steps, then the step kernel(s) alone between the two state buffers."""
     lat.step(3)
     torch.cuda.synchronize()
     s, e = ev(), ev()
@@ -453,11 +485,11 @@ def time_ddf(torch, lks, inputs, workloads, dev, ev):
     torch.cuda.synchronize()
     tk = s.elapsed_time(e) / k * 1e-3
     cells = lat.nx * lat.ny
-    res = {"workload": workloads.RIEMANN_2048_DDF["name"], "MLUPS": round(cells / t / 1e6, 1),
-           "us_per_step": round(t * 1e6, 1), "kernel": DDF_KERNEL, "kernel_us": round(tk * 1e6, 1),
-           "bytes_per_lup": BYTES_F32_DDF,
-           "GBps_model": round(BYTES_F32_DDF * cells / tk / 1e9, 1),
-           "frac_hbm": round(BYTES_F32_DDF * cells / tk / 1e9 / HBM_PEAK_GBPS, 4),
+    res = {"workload": name, "MLUPS": round(cells / t / 1e6, 1),
+           "us_per_step": round(t * 1e6, 1), "kernel": kernel, "kernel_us": round(tk * 1e6, 1),
+           "bytes_per_lup": bpl,
+           "GBps_model": round(bpl * cells / tk / 1e9, 1),
+           "frac_hbm": round(bpl * cells / tk / 1e9 / HBM_PEAK_GBPS, 4),
            "faults": lat.check()}
     del lat
     torch.cuda.empty_cache()

@@ -32,10 +32,12 @@
 
 // FP32 workgroup tile (cells) of the single-distribution kernel and the
 // minimum waves per SIMD its register allocation must allow (0 = compiler).
-// Measured at 2048^2: 16 x 8 349 us, 32 x 8 357, 64 x 4 374, 32 x 4 379; a
-// forced four waves per SIMD spills and gains nothing.
+// Measured at 2048^2 (us per step): 32 x 8 290.0, 32 x 4 289.7, 64 x 4 293.2,
+// 64 x 2 300.5, 16 x 8 324.9, 64 x 8 327.6, 32 x 16 339.2; rows of 16 cells
+// are half a 128-byte line, and the staging of 16-wide tiles alone takes as
+// long as the whole step of 32-wide ones.
 #ifndef LKS_Q25_TX
-#define LKS_Q25_TX 16
+#define LKS_Q25_TX 32
 #endif
 #ifndef LKS_Q25_TY
 #define LKS_Q25_TY 8
@@ -57,6 +59,14 @@
 #endif
 #ifndef LKS_DDF_WAVES
 #define LKS_DDF_WAVES 2
+#endif
+// FP32 tile of the double distribution's g kernel (its own launch grid): as
+// for the single distribution, rows of 32 cells stage whole 128-byte lines
+#ifndef LKS_DDF_G_TX
+#define LKS_DDF_G_TX 32
+#endif
+#ifndef LKS_DDF_G_TY
+#define LKS_DDF_G_TY 8
 #endif
 
 namespace lks {
@@ -119,30 +129,35 @@ __device__ __forceinline__ void hermite_h(R u, R tm1, R (&h)[5])
 // f^eq_i - w_i rho0 for all 25 populations from (rho - rho0, rho, u, theta - 1),
 // with the leading "1" of the expansion taken out so nothing cancels:
 // f^eq_ab = w_a w_b rho (1 + Px~_a + sum_nx Px_a[nx] Sy~_b[4 - nx]).
-template <typename R, typename F>
-__device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& use)
-{
-    R hx[5], hy[5];
-    hermite_h(ux, tm1, hx);
-    hermite_h(uy, tm1, hy);
+// Deq25 holds the per-cell factors; group<A>() gives the five populations of
+// x-node A, d2q25_deq all 25.
+template <typename R> struct Deq25 {
+    R hx[5];
     R sy[5][5];           // Sy~_b[m] = sum_{n=1..m} hy[n] He_n(xi_b)/n!
+    R drho, rho;
+    __device__ __forceinline__ Deq25(R drho_, R rho_, R ux, R uy, R tm1) : drho(drho_), rho(rho_)
+    {
+        R hy[5];
+        hermite_h(ux, tm1, hx);
+        hermite_h(uy, tm1, hy);
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
-        sy[b][0] = R(0);
+        for (int b = 0; b < 5; ++b) {
+            sy[b][0] = R(0);
 #pragma unroll
-        for (int m = 1; m < 5; ++m) sy[b][m] = sy[b][m - 1] + hy[m] * R(gh5_he(b, m));
+            for (int m = 1; m < 5; ++m) sy[b][m] = sy[b][m - 1] + hy[m] * R(gh5_he(b, m));
+        }
     }
     // the population loops are unrolled by templates: a pragma gives up when
     // the caller's per-population body is large, and the callers index
     // register arrays by the population
-    sfor25<5>([&](auto ac) {
-        constexpr int a = decltype(ac)::value;
+    template <int A, typename F> __device__ __forceinline__ void group(F&& use) const
+    {
         R px[5];
         R pt = R(0);
         px[0] = R(1);
 #pragma unroll
         for (int n = 1; n < 5; ++n) {
-            px[n] = hx[n] * R(gh5_he(a, n));
+            px[n] = hx[n] * R(gh5_he(A, n));
             pt += px[n];
         }
         sfor25<5>([&](auto bc) {
@@ -150,9 +165,16 @@ __device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& 
             R s = pt + sy[b][4];
 #pragma unroll
             for (int n = 1; n < 4; ++n) s += px[n] * sy[b][4 - n];
-            use(a, b, R(gh5_w(a) * gh5_w(b)) * (rho * s + drho));
+            use(A, b, R(gh5_w(A) * gh5_w(b)) * (rho * s + drho));
         });
-    });
+    }
+};
+
+template <typename R, typename F>
+__device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& use)
+{
+    const Deq25<R> e(drho, rho, ux, uy, tm1);
+    sfor25<5>([&](auto ac) { e.template group<decltype(ac)::value>(use); });
 }
 
 // half van Leer slope ab/(a+b) for same-sign a, b, else 0
@@ -188,6 +210,78 @@ template <int TX, int TY> struct Tile {
     }
 };
 
+// The loads that stage a TX x TY tile and its two-cell cross halo: each
+// thread's own cell, up to HR halo-row cells and one halo-column cell, at
+// the same offsets in every population plane.  Groups of NG planes go
+// through LDS one at a time: load() puts a group's halo values in registers
+// (in flight while the previous group is computed), write() stores them and
+// the threads' own values into one LDS buffer.  Planes are kStride floats
+// apart in LDS, the last one a spare slot: a thread without a halo cell
+// loads its own cell again and writes it there, so no load or store is
+// conditional (a branch around a load makes the compiler wait for every
+// load in flight where the branches join, the prefetched group's included).
+template <typename S, int TX, int TY> struct TileStage {
+    using R = typename Store<S>::real;
+    using raw = typename Store<S>::raw;
+    using T = Tile<TX, TY>;
+    static constexpr int NT = TX * TY;
+    static constexpr int HR = (4 * TX + NT - 1) / NT;
+    static constexpr int kStride = T::kPlane + 1;
+    long long own, hoff[HR], coff;
+    int hlds[HR], clds, olds;
+
+    __device__ __forceinline__ TileStage(const D2Q25Args& a, int X0, int Y0, int tx, int ty)
+    {
+        const int nx = a.nx, ny = a.ny;
+        own = (long long)ghost_index(Y0 + ty, ny, a.bc_y) * a.L.pr + ghost_index(X0 + tx, nx, a.bc_x);
+#pragma unroll
+        for (int k = 0; k < HR; ++k) {
+            const int h = threadIdx.x + k * NT;
+            const int hr = h / TX, c = h % TX;
+            const int r = hr < 2 ? hr - 2 : TY + hr - 2;
+            const bool halo = h < 4 * TX;
+            hoff[k] = halo ? (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x)
+                           : own;
+            hlds[k] = halo ? T::rowbase(r) + c : T::kPlane;
+        }
+        coff = own;
+        clds = T::kPlane;
+        if (threadIdx.x < 4 * TY) {
+            const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
+            const int c = hc < 2 ? hc - 2 : TX + hc - 2;
+            coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
+            clds = T::rowbase(r) + c;
+        }
+        olds = T::rowbase(ty) + tx;
+    }
+    // halo values of planes p0 .. p0 + NG - 1
+    template <int NG>
+    __device__ __forceinline__ void load(const raw* __restrict__ fin, long long pp, int p0, R (&vh)[NG][HR],
+                                         R (&vc)[NG]) const
+    {
+        sfor25<NG>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            const raw* src = fin + (p0 + p) * pp;
+#pragma unroll
+            for (int k = 0; k < HR; ++k) vh[p][k] = Store<S>::to_real(src[hoff[k]]);
+            vc[p] = Store<S>::to_real(src[coff]);
+        });
+    }
+    // a group into buf (NG planes kStride apart): own values mine[Q0 ..], halo vh, vc
+    template <int NG, int Q0, int NQ>
+    __device__ __forceinline__ void write(R* buf, const R (&mine)[NQ], const R (&vh)[NG][HR], const R (&vc)[NG]) const
+    {
+        sfor25<NG>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            R* dst = buf + p * kStride;
+            dst[olds] = mine[Q0 + p];
+#pragma unroll
+            for (int k = 0; k < HR; ++k) dst[hlds[k]] = vh[p][k];
+            dst[clds] = vc[p];
+        });
+    }
+};
+
 template <int NW>
 __device__ __forceinline__ void block_sums_n(double (&acc)[kNsums], double* __restrict__ out)
 {
@@ -212,6 +306,15 @@ __device__ __forceinline__ void block_sums_n(double (&acc)[kNsums], double* __re
 template <typename S> struct Q25Waves { static constexpr int v = 1; };
 template <> struct Q25Waves<float> { static constexpr int v = LKS_Q25_WAVES > 0 ? LKS_Q25_WAVES : 1; };
 
+// One workgroup per TX x TY tile.  Every thread keeps its own cell's 25
+// values in registers (the moments need all of them first); the stencil
+// neighbours reach LDS one velocity group at a time (the five populations of
+// one x-node: the tile and its two-cell cross halo), double-buffered, so the
+// halo loads of group a + 1 are in flight while group a is computed.  Wide
+// tiles keep every row piece of a load a whole number of 128-byte lines.
+// Unlike TileStage, only the threads with a halo cell load one: here that
+// keeps the kernel at 121 registers (four waves per SIMD) and measured 7 %
+// faster than the unconditional form.
 template <typename S, int TX, int TY, bool EXT = false>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Waves<S>::v))) void d2q25_kernel(D2Q25Args a, const typename Store<S>::raw* __restrict__ fin,
                                                    typename Store<S>::raw* __restrict__ fout,
@@ -223,7 +326,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     using R = typename Store<S>::real;
     using T = Tile<TX, TY>;
     constexpr int NT = TX * TY;
-    __shared__ R lds[25 * T::kPlane];
+    constexpr int NG = 5;                      // planes per staged group
+    __shared__ R lds[2][NG * T::kPlane];
 
     const int nx = a.nx, ny = a.ny;
     const long long plane = a.plane;
@@ -245,12 +349,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     const int X = X0 + tx, Y = Y0 + ty;
     const bool active = X < nx && Y < ny;
     const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
-
-    // ---- global offsets of this thread's staging loads (the same for every
-    //      population plane): its own cell, up to HR halo-row cells and one
-    //      halo-column cell
     constexpr int HR = (4 * TX + NT - 1) / NT;
-    long long own = (long long)gyc * a.L.pr + gxc;
+    const long long own = (long long)gyc * a.L.pr + gxc;
     long long hoff[HR];
     int hlds[HR];
 #pragma unroll
@@ -271,41 +371,50 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     }
     const int olds = T::rowbase(ty) + tx;
 
-    // ---- stage 25 planes (cells + cross halo) and accumulate the moments.
+    // ---- own-cell values of all 25 planes, and the halo of group 0
+    R vin[25];
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        vin[i] = Store<S>::to_real(fin[i * a.L.pp + own]);
+    });
+    R vh[NG][HR], vc[NG];
+    auto load_group = [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        sfor25<NG>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            const typename Store<S>::raw* src = fin + (NG * g + p) * a.L.pp;
+#pragma unroll
+            for (int k = 0; k < HR; ++k) vh[p][k] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
+            vc[p] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
+        });
+    };
+    auto write_group = [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        R* buf = lds[g & 1];
+        sfor25<NG>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            R* dst = buf + p * T::kPlane;
+            dst[olds] = vin[NG * g + p];
+#pragma unroll
+            for (int k = 0; k < HR; ++k)
+                if (hlds[k] >= 0) dst[hlds[k]] = vh[p][k];
+            if (clds >= 0) dst[clds] = vc[p];
+        });
+    };
+    load_group(std::integral_constant<int, 0>{});
+
+    // ---- moments and cell state: rho, u, theta - 1, relaxation factor
     const R rho0 = R(a.rho0);
     R drho = R(0), jx = R(0), jy = R(0), edev = R(0);
-    auto moment_add = [&](int i, R v) {
-        const int ia = i / 5, ib = i % 5;
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ia = i / 5, ib = i % 5;
+        const R v = vin[i];
         drho += v;
         if (ia != 2) jx += R(gh5_xi(ia)) * v;
         if (ib != 2) jy += R(gh5_xi(ib)) * v;
         edev += R(0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))) * v;
-    };
-    // all loads are issued before the first LDS write so that the 25
-    // planes' latencies overlap instead of adding up
-    R vin[25], vh[HR][25], vc[25];
-    sfor25<25>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        const typename Store<S>::raw* src = fin + i * a.L.pp;
-        vin[i] = Store<S>::to_real(src[own]);
-#pragma unroll
-        for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
-        vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
     });
-    sfor25<25>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        R* dst = lds + i * T::kPlane;
-        const R v = vin[i];
-        dst[olds] = v;
-        moment_add(i, v);
-#pragma unroll
-        for (int k = 0; k < HR; ++k)
-            if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];
-        if (clds >= 0) dst[clds] = vc[i];
-    });
-    __syncthreads();
-
-    // ---- cell state: rho, u, theta - 1, relaxation factor
     const R rho = rho0 + drho;
     const R irho = R(1) / rho;
     const R ux = jx * irho, uy = jy * irho;
@@ -313,6 +422,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     const R tm1 = (edev - drho) * irho - R(0.5) * (ux * ux + uy * uy);
     const R A = R(a.dt / a.dx);
     const R B = R(a.dt) * rho * (R(1) + tm1) / R(a.mu);   // dt / tau
+    const Deq25<R> eq(drho, rho, ux, uy, tm1);
+
+    write_group(std::integral_constant<int, 0>{});
+    __syncthreads();
 
     const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
                        T::rowbase(ty + 2)};
@@ -321,44 +434,54 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     bool first = true;
     const long long off = (long long)Y * nx + X;
     const long long poff = a.L.at(0, Y, X);
-    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
-        const int i = 5 * ia + ib;
-        const R* t = lds + i * T::kPlane;
-        const R d = t[rb[2] + tx];
-        const R fneq = d - deq;
-        const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
-        const R x = fneq * rcp(feq);
-        kl += (fneq * x) * kl_series(x);           // series branch; fallback below
-        xmin = first ? x : fmin(xmin, x);
-        xmax = first ? fabs(x) : fmax(xmax, fabs(x));
-        feqmin = first ? feq : fmin(feqmin, feq);
-        first = false;
-        neq += fabs(fneq);
-        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
-        pxx += vx * vx * fneq;
-        pxy += vx * vy * fneq;
-        pyy += vy * vy * fneq;
-        const R e = R(0.5) * (vx * vx + vy * vy);
-        qx += vx * e * fneq;
-        qy += vy * e * fneq;
-        // flux divergence (dimension by dimension, upwind + van Leer)
-        R div = R(0);
-        if (ia != 2) {
-            const R* row = t + rb[2] + tx;
-            div += vx * (ia > 2 ? flux_diff<R, 1>(row[-2], row[-1], d, row[1], R(0))
-                                : flux_diff<R, -1>(R(0), row[-1], d, row[1], row[2]));
+    sfor25<5>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        // the next group's halo is in flight while this one is computed
+        if constexpr (g + 1 < 5) load_group(std::integral_constant<int, g + 1>{});
+        const R* buf = lds[g & 1];
+        eq.template group<g>([&](int ia, int ib, R deq) {
+            const int i = 5 * ia + ib;
+            const R* t = buf + ib * T::kPlane;
+            const R d = vin[i];
+            const R fneq = d - deq;
+            const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
+            const R x = fneq * rcp(feq);
+            kl += (fneq * x) * kl_series(x);           // series branch; fallback below
+            xmin = first ? x : fmin(xmin, x);
+            xmax = first ? fabs(x) : fmax(xmax, fabs(x));
+            feqmin = first ? feq : fmin(feqmin, feq);
+            first = false;
+            neq += fabs(fneq);
+            const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+            pxx += vx * vx * fneq;
+            pxy += vx * vy * fneq;
+            pyy += vy * vy * fneq;
+            const R e = R(0.5) * (vx * vx + vy * vy);
+            qx += vx * e * fneq;
+            qy += vy * e * fneq;
+            // flux divergence (dimension by dimension, upwind + van Leer)
+            R div = R(0);
+            if (ia != 2) {
+                const R* row = t + rb[2] + tx;
+                div += vx * (ia > 2 ? flux_diff<R, 1>(row[-2], row[-1], d, row[1], R(0))
+                                    : flux_diff<R, -1>(R(0), row[-1], d, row[1], row[2]));
+            }
+            if (ib != 2) {
+                div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
+                                    : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
+            }
+            if (active) fout[i * a.L.pp + poff] = Store<S>::from_real(d - A * div + B * (deq - d));
+        });
+        if constexpr (g + 1 < 5) {
+            write_group(std::integral_constant<int, g + 1>{});
+            __syncthreads();
         }
-        if (ib != 2) {
-            div += vy * (ib > 2 ? flux_diff<R, 1>(t[rb[0] + tx], t[rb[1] + tx], d, t[rb[3] + tx], R(0))
-                                : flux_diff<R, -1>(R(0), t[rb[1] + tx], d, t[rb[3] + tx], t[rb[4] + tx]));
-        }
-        if (active) fout[i * a.L.pp + poff] = Store<S>::from_real(d - A * div + B * (deq - d));
     });
     if (!(xmax <= KlCut<R>::v)) {
         // rare: some population far from equilibrium (or NaN): the closed form
         kl = R(0);
         d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
-            const R d = lds[(5 * ia + ib) * T::kPlane + rb[2] + tx];
+            const R d = vin[5 * ia + ib];
             const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
             kl += feq * kl_phi((d - deq) * rcp(feq));
         });
@@ -383,14 +506,15 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
         }
         if constexpr (EXT) {
             // A separate pass on opaque copies (pin) of the moments and of the
-            // staged populations, after the base arithmetic: no base expression
-            // gains a use, so the base results do not depend on the extension.
+            // cell's populations, after the base arithmetic: no base
+            // expression gains a use, so the base results do not depend on
+            // the extension.
             const R drho_p = pin(drho), rho_p = pin(rho), ux_p = pin(ux), uy_p = pin(uy),
                     tm1_p = pin(tm1), rho0_p = pin(rho0);
             ExtAcc<R> xa;
             const ExtNeed need(a.x.mask);
             d2q25_deq<R>(drho_p, rho_p, ux_p, uy_p, tm1_p, [&](int ia, int ib, R deq) {
-                const R d = pin(lds[(5 * ia + ib) * T::kPlane + rb[2] + tx]);
+                const R d = pin(vin[5 * ia + ib]);
                 const R w = R(gh5_w(ia) * gh5_w(ib));
                 const R fneq = d - deq;
                 const R x = fneq * rcp(w * rho0_p + deq);
@@ -827,8 +951,9 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
 {
     using R = typename Store<S>::real;
     using T = Tile<TX, TY>;
-    constexpr int NT = TX * TY;
-    __shared__ R lds[25 * T::kPlane];
+    constexpr int NG = 5;                      // planes per staged group
+    constexpr int kStride = TileStage<S, TX, TY>::kStride;
+    __shared__ R lds[2][NG * kStride];
 
     const int nx = a.nx, ny = a.ny;
     const long long plane = a.plane;
@@ -848,33 +973,24 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
     const int X0 = tile_x * TX, Y0 = tile_y * TY;
     const int X = X0 + tx, Y = Y0 + ty;
     const bool active = X < nx && Y < ny;
-    const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
-
-    constexpr int HR = (4 * TX + NT - 1) / NT;
-    const long long own = (long long)gyc * a.L.pr + gxc;
-    long long hoff[HR];
-    int hlds[HR];
-#pragma unroll
-    for (int k = 0; k < HR; ++k) {
-        const int h = threadIdx.x + k * NT;
-        const int hr = h / TX, c = h % TX;
-        const int r = hr < 2 ? hr - 2 : TY + hr - 2;
-        hoff[k] = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
-        hlds[k] = h < 4 * TX ? T::rowbase(r) + c : -1;
-    }
-    long long coff = 0;
-    int clds = -1;
-    if (threadIdx.x < 4 * TY) {
-        const int hc = threadIdx.x % 4, r = threadIdx.x / 4;
-        const int c = hc < 2 ? hc - 2 : TX + hc - 2;
-        coff = (long long)ghost_index(Y0 + r, ny, a.bc_y) * a.L.pr + ghost_index(X0 + c, nx, a.bc_x);
-        clds = T::rowbase(r) + c;
-    }
-    const int olds = T::rowbase(ty) + tx;
+    const TileStage<S, TX, TY> st(a, X0, Y0, tx, ty);
+    constexpr int HR = TileStage<S, TX, TY>::HR;
     const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
                        T::rowbase(ty + 2)};
     const long long off = (long long)Y * nx + X;
     const long long poff = a.L.at(0, Y, X);
+
+    // own-cell g values (registers), then g's stencil neighbours one velocity
+    // group at a time through a double-buffered LDS tile, the next group's
+    // halo in flight while this one is computed
+    const typename Store<S>::raw* gin = fin + 25 * a.L.pp;
+    R gc[25];
+    sfor25<25>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        gc[i] = Store<S>::to_real(gin[i * a.L.pp + st.own]);
+    });
+    R vh[NG][HR], vc[NG];
+    st.template load<NG>(gin, a.L.pp, 0, vh, vc);
 
     // the cell state from the f kernel (own cell only; ghost threads stage)
     R drho = R(0), ux = R(0), uy = R(0), tm1 = R(0), qgx = R(0), qgy = R(0);
@@ -887,30 +1003,6 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
         qgx = aux[4 * plane];
         qgy = aux[5 * plane];
     }
-
-    R gc[25];
-    {
-        R vh[HR][25], vc[25];
-        sfor25<25>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const typename Store<S>::raw* src = fin + (25 + i) * a.L.pp;
-            gc[i] = Store<S>::to_real(src[own]);
-#pragma unroll
-            for (int k = 0; k < HR; ++k) vh[k][i] = hlds[k] >= 0 ? Store<S>::to_real(src[hoff[k]]) : R(0);
-            vc[i] = clds >= 0 ? Store<S>::to_real(src[coff]) : R(0);
-        });
-        sfor25<25>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            R* dst = lds + i * T::kPlane;
-            dst[olds] = gc[i];
-#pragma unroll
-            for (int k = 0; k < HR; ++k)
-                if (hlds[k] >= 0) dst[hlds[k]] = vh[k][i];
-            if (clds >= 0) dst[clds] = vc[i];
-        });
-    }
-    __syncthreads();
-
     const R rho0 = R(a.rho0);
     const R gfac = R(a.cv) - R(1);
     const R rho = rho0 + drho;
@@ -918,6 +1010,11 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
     const R A = R(a.dt / a.dx);
     const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
     const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
+    const Deq25<R> eq(drho, rho, ux, uy, tm1);
+
+    st.template write<NG, 0>(lds[0], gc, vh, vc);
+    __syncthreads();
+
     const int own_lds = rb[2] + tx;
     auto div_of = [&](const R* t, R d, int ia, int ib, R vx, R vy) {
         R div = R(0);
@@ -932,15 +1029,24 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
         }
         return div;
     };
-    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
-        const int i = 5 * ia + ib;
-        const R w = R(gh5_w(ia) * gh5_w(ib));
-        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
-        const R dg = gc[i];
-        const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
-        const R dgs = w * (qgx * vx + qgy * vy);
-        const R divg = div_of(lds + i * T::kPlane, dg, ia, ib, vx, vy);
-        if (active) fout[(25 + i) * a.L.pp + poff] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
+    sfor25<5>([&](auto gcn) {
+        constexpr int g = decltype(gcn)::value;
+        if constexpr (g + 1 < 5) st.template load<NG>(gin, a.L.pp, NG * (g + 1), vh, vc);
+        const R* buf = lds[g & 1];
+        eq.template group<g>([&](int ia, int ib, R deq) {
+            const int i = 5 * ia + ib;
+            const R w = R(gh5_w(ia) * gh5_w(ib));
+            const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
+            const R dg = gc[i];
+            const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
+            const R dgs = w * (qgx * vx + qgy * vy);
+            const R divg = div_of(buf + ib * kStride, dg, ia, ib, vx, vy);
+            if (active) fout[(25 + i) * a.L.pp + poff] = Store<S>::from_real(dg - A * divg - B1 * gneq + B12 * dgs);
+        });
+        if constexpr (g + 1 < 5) {
+            st.template write<NG, NG * (g + 1)>(lds[(g + 1) & 1], gc, vh, vc);
+            __syncthreads();
+        }
     });
 }
 
@@ -949,6 +1055,9 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
                                   uint8_t* flags, double* partials, unsigned long long* faults,
                                   hipStream_t s)
 {
+    // the g kernel writes no partial sums: it runs on a tile grid of its own
+    constexpr int GX = sizeof(typename Store<S>::real) == 4 ? LKS_DDF_G_TX : TX;
+    constexpr int GY = sizeof(typename Store<S>::real) == 4 ? LKS_DDF_G_TY : TY;
     using raw = typename Store<S>::raw;
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
@@ -960,7 +1069,13 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
         d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
-    d2q25_ddf_g_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(a, (const raw*)fin, (raw*)fout);
+    D2Q25Args ag = a;
+    ag.tile_x = GX;
+    ag.tile_y = GY;
+    ag.tiles_x = (a.nx + GX - 1) / GX;
+    ag.tiles_y = (a.ny + GY - 1) / GY;
+    ag.nblocks = ag.tiles_x * ag.tiles_y;
+    d2q25_ddf_g_kernel<S, GX, GY><<<dim3(ag.nblocks), dim3(GX * GY), 0, s>>>(ag, (const raw*)fin, (raw*)fout);
     return hipGetLastError();
 }
 

@@ -50,7 +50,9 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=100)
-    p.add_argument("--warmup", type=int, default=10)
+    # untimed steps first: under sustained load the chip's clocks dip a few
+    # milliseconds in and settle some 15 ms later (about 60 steps here)
+    p.add_argument("--warmup", type=int, default=60)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=40)
     p.add_argument("--forms", action="store_true",

@@ -105,9 +105,9 @@ enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u, LKS_S_QE = 16
  *                  (|v_i|^2/4 - 1) with the translational heat flux q_f =
  *                  1/2 sum |v - u|^2 (v - u) f, g* = g^eq + w_i (q_g . v_i) with
  *                  q_g = sum (v - u) g.  Both distributions take the same van
- *                  Leer fluxes.  State [50][ny][nx]: f deviations f_i - w_i rho0
- *                  (planes 0..24), then g deviations g_i - (C_v - 1) w_i rho0
- *                  (planes 25..49).  Five sensor planes: 0 S_KL = |sum f
+ *                  Leer fluxes.  State: 50 populations per cell (in the configured
+ *                  layout), f deviations f_i - w_i rho0 (0..24), then g
+ *                  deviations g_i - (C_v - 1) w_i rho0 (25..49).  Five sensor planes: 0 S_KL = |sum f
  *                  ln(f/f^eq)| + |sum g ln(g/g^eq)|, 1 S_NEQ = sum |f^neq| +
  *                  sum |g^neq|, 2 S_PI of f, 3 S_Q = |sum v g^neq + sum v |v|^2/2
  *                  f^neq|, 4 S_QE = sum |f* - f^eq| + sum |g* - g^eq| (eqs.
@@ -242,8 +242,8 @@ lks_status lks_restore(lks_ctx* ctx, int32_t pop_index, int64_t steps_done);
  * sensors and flags hold the last step's values. */
 lks_status lks_step(lks_ctx* ctx, int32_t nsteps, int32_t fused);
 
-/* One fused step from the state src into dst (both [Q][ny][nx] in the
- * context's dtype, distinct, neither need be pop[0]/pop[1]); sensors and
+/* One fused step from the state src into dst (both Q*ny*nx values in the
+ * context's layout and dtype, distinct, neither need be pop[0]/pop[1]); sensors and
  * flags receive this step's values, the sums buffer and the step count are
  * left unchanged.  Used to recompute trajectory segments from checkpoints. */
 lks_status lks_step_from(lks_ctx* ctx, const void* src, void* dst);

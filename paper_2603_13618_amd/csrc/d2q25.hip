@@ -16,12 +16,14 @@
 // Layout and staging: deviations d_i = f_i - w_i rho0 (the constant part
 // cancels in every flux difference), population i of cell (x, y) at
 // i * pp + y * pr + x (PopLayout: plane-major [25][ny][nx] or row-interleaved
-// [ny][25][nx]).  A TX x TY workgroup
-// tile stages all 25 planes of its cells plus a two-cell cross-shaped halo in
-// LDS once, then every stencil read comes from LDS.  Tiles are assigned to
-// workgroups so that the eight XCDs each sweep their own band of tile
-// columns row by row: vertically adjacent tiles run on the same XCD shortly
-// after one another, so halo rows are served by that XCD's L2.
+// [ny][25][nx]).  One workgroup per TX x TY tile: each thread keeps its own
+// cell's populations in registers, and the stencil neighbours (the tile and
+// a two-cell cross-shaped halo) reach LDS one velocity group at a time,
+// double-buffered (the double distribution's f kernel stages all 25 f planes
+// at once).  Tiles are assigned to workgroups so that the eight XCDs each
+// sweep their own band of tile columns row by row: vertically adjacent tiles
+// run on the same XCD shortly after one another, so halo rows are served by
+// that XCD's L2.
 //
 // The double distribution (f, g; quasi-equilibrium collision) has its own
 // kernel further down: the same fluxes on 50 planes, two passes over the
@@ -568,17 +570,17 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
 // sum |g^neq|, S_PI of f, |sum v g^neq + sum v |v|^2/2 f^neq|, and the QE
 // sensor sum |f* - f^eq| + sum |g* - g^eq| (eqs. HKL-sensor, sensor-neq-kin,
 // sensor-TauNS-kin, sensor-qNSF-kin-ryk, Sensor-qe-kin).
-// Storage: [50][ny][nx], f deviations from w rho0, then g deviations from
-// (C_v - 1) w rho0.
+// Storage: 50 populations per cell, f deviations from w rho0, then g
+// deviations from (C_v - 1) w rho0.
 //
-// f and g are staged one after the other through one 25-plane LDS buffer
-// (the tile and its two-cell cross halo, as in d2q25_kernel): the own-cell g
-// values stay in registers from the start (the moments need them).  Pass 1
-// over the velocities takes the non-equilibrium parts of both: the sensors
-// and the heat fluxes q_f = 1/2 sum |c|^2 c f^neq, q_g = sum c g^neq (c = v - u;
-// the equilibria carry none, so no cancellation), and keeps the 25
-// equilibrium deviations for pass 2.  Pass 2 applies the collision and the
-// fluxes to f; g is then staged into the same buffer and updated.
+// The step is two kernels.  d2q25_ddf_kernel stages f (25 planes, the tile
+// and its two-cell cross halo) in LDS and keeps the own-cell g values in
+// registers (the moments need them).  Pass 1 over the velocities takes the
+// non-equilibrium parts of both: the sensors and the heat fluxes q_f = 1/2
+// sum |c|^2 c f^neq, q_g = sum c g^neq (c = v - u; the equilibria carry none,
+// so no cancellation), and keeps the 25 equilibrium deviations for pass 2,
+// which applies the collision and the fluxes to f and hands drho, u, T - 1
+// and q_g of each cell to d2q25_ddf_g_kernel, which updates g.
 // ---------------------------------------------------------------------------
 // the register hint applies to FP32 storage only (FP64 values take two
 // registers each: there the hint would spill hundreds)

@@ -470,8 +470,9 @@ def time_q25(torch, lks, inputs, workloads, dev, ev):
 
 
 def time_d2q25(torch, ev, lat, k, name, kernel, bpl):
-    """Whole steps, then the step kernel(s) alone between the two state buffers."""
-    lat.step(3)
+    """Whole steps, then the step kernel(s) alone between the two state buffers
+    (after untimed steps that let the clocks settle)."""
+    lat.step(20)
     torch.cuda.synchronize()
     s, e = ev(), ev()
     s.record()

@@ -256,7 +256,8 @@ lks_status lks_current(const lks_ctx* ctx, int32_t* pop_index, int64_t* steps_do
 lks_status lks_moments(lks_ctx* ctx, double* rho, double* ux, double* uy, double* T);
 
 /* Synchronise the stream and copy to host memory: what = 0 current
- * populations, 1 sensors, 2 flags, 3 sums.  bytes must equal the buffer size. */
+ * populations (in the configured layout), 1 sensors, 2 flags, 3 sums.  bytes
+ * must equal the buffer size. */
 lks_status lks_read_host(lks_ctx* ctx, int32_t what, void* host_dst, size_t bytes);
 
 /* Synchronise; report the number of positivity-fault cells counted since

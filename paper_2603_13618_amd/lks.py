@@ -140,6 +140,15 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def same_layout(t, ref):
+    """True if tensor t holds a state exactly as ref does: shape, dtype,
+    device, element strides (those of dimensions of length 1 carry no
+    information) and no storage offset."""
+    strides = all(a == b for a, b, n in zip(t.stride(), ref.stride(), ref.shape) if n > 1)
+    return (tuple(t.shape) == tuple(ref.shape) and t.dtype == ref.dtype and t.device == ref.device
+            and strides and t.storage_offset() == 0)
+
+
 def _stream_handle(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -253,10 +262,7 @@ class Lattice:
         return self._alloc_state(self.pop[0].dtype, self.device)
 
     def _state_arg(self, t, what):
-        ok = (tuple(t.shape) == tuple(self.pop[0].shape) and t.dtype == self.pop[0].dtype
-              and t.device == self.pop[0].device and t.stride() == self.pop[0].stride()
-              and t.storage_offset() == 0)
-        if not ok:
+        if not same_layout(t, self.pop[0]):
             raise ValueError(f"{what} must be a [Q, ny, nx] {self.pop[0].dtype} state in this "
                              f"context's layout (strides {self.pop[0].stride()}): use new_state()")
         return _ptr(t)

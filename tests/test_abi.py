@@ -7,6 +7,7 @@ import re
 import subprocess
 
 import pytest
+import torch
 
 from paper_2603_13618_amd import lks
 
@@ -154,3 +155,16 @@ def test_null_context_is_rejected(name):
     if name == "lks_step":
         args = [None, 1, 1]
     assert fn(*args) == 1
+
+
+def test_state_layout_check_on_host():
+    # a row-interleaved state is a [Q, ny, nx] view of a [ny, Q, nx] buffer
+    Q, ny, nx = 9, 7, 16
+    rows = torch.zeros((ny, Q, nx)).permute(1, 0, 2)
+    assert lks.same_layout(torch.empty_like(rows), rows)
+    assert not lks.same_layout(torch.zeros((Q, ny, nx)), rows)         # plane-major
+    assert not lks.same_layout(rows.double(), rows)
+    assert not lks.same_layout(torch.zeros((ny + 1, Q, nx)).permute(1, 0, 2)[:, 1:], rows)
+    # with one row both layouts are the same arrangement of the same elements
+    one = torch.zeros((1, Q, nx)).permute(1, 0, 2)
+    assert lks.same_layout(torch.zeros((Q, 1, nx)), one)

@@ -191,7 +191,13 @@ typedef struct {
                              exceed the 256 MB last-level cache), 1 plain,
                              2 non-temporal (a launch hint only: results are
                              identical)                                        */
-    int32_t launch_reserved; /* must be 0                                       */
+    int32_t launch_steps; /* fused D2Q9 steps per launch: 0 or 1 one, 2 two
+                             (temporal blocking: the state crosses HBM once
+                             per two steps; D2Q9 without extension sensors;
+                             an odd last step runs alone).  A launch hint:
+                             the results are the same bits, but the state
+                             changes buffer once per launch, so lks_current
+                             names the buffer that holds it                 */
 } lks_config;
 
 typedef struct {

@@ -127,27 +127,30 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
     if constexpr (SENSE) {
         R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
         R xmax = R(0), xmin = R(0), feqmin = R(0);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const R fneq = d[i] - deq[i];
-            const R feq = w9<R>(i) * rho0 + deq[i];
-            const R x = fneq * rcp(feq);
-            // S_KL term feq phi(x) = fneq x p(x) on the series branch
-            kl += (fneq * x) * kl_series(x);
-            xmax = i == 0 ? fabs(x) : fmax(xmax, fabs(x));
-            xmin = i == 0 ? x : fmin(xmin, x);
-            feqmin = i == 0 ? feq : fmin(feqmin, feq);
-            neq += fabs(fneq);
-            if (cx9(i) != 0) pxx += fneq;
-            if (cy9(i) != 0) pyy += fneq;
-            if (cx9(i) * cy9(i) != 0) pxy += R(cx9(i) * cy9(i)) * fneq;
-        }
-        if (!(xmax <= KlCut<R>::v)) {       // rare: far from equilibrium (or NaN)
-            kl = R(0);
+        {   // multiply-adds fuse within one expression only: the same bits in every kernel
+#pragma clang fp contract(on)
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
+                const R fneq = d[i] - deq[i];
                 const R feq = w9<R>(i) * rho0 + deq[i];
-                kl += feq * kl_phi((d[i] - deq[i]) * rcp(feq));
+                const R x = fneq * rcp(feq);
+                // S_KL term feq phi(x) = fneq x p(x) on the series branch
+                kl += (fneq * x) * kl_series(x);
+                xmax = i == 0 ? fabs(x) : fmax(xmax, fabs(x));
+                xmin = i == 0 ? x : fmin(xmin, x);
+                feqmin = i == 0 ? feq : fmin(feqmin, feq);
+                neq += fabs(fneq);
+                if (cx9(i) != 0) pxx += fneq;
+                if (cy9(i) != 0) pyy += fneq;
+                if (cx9(i) * cy9(i) != 0) pxy += R(cx9(i) * cy9(i)) * fneq;
+            }
+            if (!(xmax <= KlCut<R>::v)) {       // rare: far from equilibrium (or NaN)
+                kl = R(0);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const R feq = w9<R>(i) * rho0 + deq[i];
+                    kl += feq * kl_phi((d[i] - deq[i]) * rcp(feq));
+                }
             }
         }
         out.fault = !(feqmin > R(0)) || !(xmin > R(-1)) || !(kl == kl);
@@ -589,6 +592,245 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     if (y0 < y1) store_row(y1 - 1);
     if (nfault) atomicAdd(faults, (unsigned long long)nfault);
     block_sums(acc, partials + (long long)blockIdx.x * kNsums);
+}
+
+// Two fused steps per pass over HBM (temporal blocking): the API keeps
+// only the last step's sensors and flags, so a wave can advance its cells two
+// steps from one read of the state.  Each wave owns a strip of kSweepW = 60
+// columns and kSweepH rows: its 64 lanes hold the strip and a two-column ring
+// (periodic), one column per lane, and the wave sweeps down the rows with its
+// state in registers.  Raw row q arrives; step A runs on row q - 1 (lanes 1 to
+// 62: the strip and a one-column ring), with the x neighbours from the
+// adjacent lanes (DPP wave shifts) and the y neighbours from the two previous
+// raw rows; its post-collision values, rounded to the storage type as a stored
+// state would be, feed step B on row q - 2 (lanes 2 to 61) in the same way.
+// The strip's rows plus a two-row ring are read once; step B stores
+// populations, sensors and flags.  No LDS and no barrier until the final sums.
+// Each cell's sums and faults are counted by the wave that owns it, for both
+// steps.  The loads of raw rows q + 1 and q + 2 are in flight while row q is
+// used.  kSweepH = 16 rows per wave: short strips give more independent waves,
+// which hides latency better than the shorter ring of tall strips saves bytes.
+// TWO = false: one step (the odd step of a run), stored.  Each cell's
+// arithmetic is cell_update, as in the one-step kernels, so the results are
+// bit-identical.
+constexpr int kSweepW = kWave - 4;
+constexpr int kSweepH = 16;
+
+// Periodic index for j in [-2, n + 1] (exact for n >= 2; n = 1 maps every j
+// to 0).  Indexes further out only feed cells that are not stored: any
+// in-range index serves them, so they are clamped.
+__device__ __forceinline__ int wrap_index(int j, int n)
+{
+    j += j < 0 ? n : 0;
+    j -= j >= n ? n : 0;
+    return min(max(j, 0), n - 1);
+}
+
+// The value of lane l - CX (CX = +1: from the lane below, -1: from the lane
+// above); lanes whose source is outside the wave get 0.
+template <int CX>
+__device__ __forceinline__ float lane_shift(float v)
+{
+    if constexpr (CX == 0) {
+        return v;
+    } else {
+        constexpr int ctrl = CX > 0 ? 0x138 : 0x130;    // wave_shr:1 / wave_shl:1
+        return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl,
+                                                                     0xf, 0xf, false));
+    }
+}
+template <int CX>
+__device__ __forceinline__ double lane_shift(double v)
+{
+    if constexpr (CX == 0) {
+        return v;
+    } else {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const float lo = lane_shift<CX>(__builtin_bit_cast(float, (unsigned)u));
+        const float hi = lane_shift<CX>(__builtin_bit_cast(float, (unsigned)(u >> 32)));
+        return __builtin_bit_cast(double, (unsigned long long)__builtin_bit_cast(unsigned, lo) |
+                                              ((unsigned long long)__builtin_bit_cast(unsigned, hi) << 32));
+    }
+}
+
+// Pre-step values of a cell at row y: population i from row y - cy_i (prev2,
+// prev, cur for cy = +1, 0, -1) and lane l - cx_i.
+template <typename R>
+__device__ __forceinline__ void gather_pull(R (&d)[9], const R (&prev2)[9], const R (&prev)[9], const R (&cur)[9])
+{
+    static_for<9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int cy = cy9(i), cx = cx9(i);
+        const R v = cy > 0 ? prev2[i] : (cy == 0 ? prev[i] : cur[i]);
+        d[i] = lane_shift<cx>(v);
+    });
+}
+
+template <typename S, bool TWO>
+__global__ __launch_bounds__(kBlock) void d2q9_fused2_kernel(
+    D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
+    typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ part_a,
+    double* __restrict__ part_b, unsigned long long* __restrict__ faults)
+{
+    using R = typename Store<S>::real;
+    const int nx = a.nx, ny = a.ny;
+    const long long plane = a.plane;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int strips = (nx + kSweepW - 1) / kSweepW, segs = (ny + kSweepH - 1) / kSweepH;
+    const int wid = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const bool has = wid < strips * segs;
+    const int X0 = (wid % strips) * kSweepW, Yb = (wid / strips) * kSweepH;
+    const int Ye = min(Yb + kSweepH, ny);
+    const int X = X0 - 2 + lane;                  // this lane's column
+    const int gx = wrap_index(X, nx);
+    const bool own_col = lane >= 2 && lane < kSweepW + 2 && X < nx;
+
+    constexpr bool F32 = sizeof(R) == 4;
+    const R rho0 = F32 ? R(a.rho0_f) : R(a.rho0);
+    const R inv_tau = F32 ? R(a.inv_tau_f) : R(1.0 / a.tau);
+    R th[3][2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        th[k][0] = F32 ? R(a.thr_f[k][0]) : R(a.thr[k][0]);
+        th[k][1] = F32 ? R(a.thr_f[k][1]) : R(a.thr[k][1]);
+    }
+    auto level_of = [&](const CellSense<R>& cs) {
+        int level = 0;
+        const R sv[3] = {cs.kl, cs.neq, cs.pi};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (a.mask & (1u << k)) {
+                const int l = (sv[k] > th[k][0]) + (sv[k] > th[k][1]);
+                level = l > level ? l : level;
+            }
+        }
+        return cs.fault ? uint8_t(0x82) : uint8_t(level);
+    };
+    auto store_cell = [&](int Y, const R (&d)[9], const CellSense<R>& cs) {
+        const long long off = (long long)Y * nx + X;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fout[a.L.at(i, Y, X)] = Store<S>::from_real(d[i]);
+        sens[off] = cs.kl;
+        sens[plane + off] = cs.neq;
+        sens[2 * plane + off] = cs.pi;
+        flags[off] = level_of(cs);
+    };
+    auto add_sums = [&](double (&acc)[kNsums], unsigned& nf, R drho, R jx, R jy, const CellSense<R>& cs) {
+        acc[0] += (double)drho;
+        acc[1] += (double)jx;
+        acc[2] += (double)jy;
+        acc[4] += (double)cs.kl;
+        acc[5] += (double)cs.neq;
+        acc[6] += (double)cs.pi;
+        nf += cs.fault ? 1u : 0u;
+    };
+    auto load_row = [&](int q, R (&r)[9]) {
+        const int gy = wrap_index(q, ny);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) r[i] = Store<S>::to_real(fin[a.L.at(i, gy, gx)]);
+    };
+
+    double acc_a[kNsums], acc_b[kNsums];
+#pragma unroll
+    for (int k = 0; k < kNsums; ++k) acc_a[k] = acc_b[k] = 0.0;
+    unsigned nfault = 0;
+
+    if (has) {
+        // raw rows qs .. qe; step A on rows qs + 1 .. qe - 1, step B (TWO) on Yb .. Ye - 1
+        const int qs = Yb - (TWO ? 2 : 1), qe = Ye + (TWO ? 1 : 0);
+        R prev2[9], prev[9], cur[9], nxt[9] = {}, nxt2[9] = {};
+        R aprev2[9], aprev[9];
+        load_row(qs, prev2);
+        load_row(qs + 1, prev);
+        load_row(qs + 2, cur);
+        if (qs + 3 <= qe) load_row(qs + 3, nxt);
+        for (int q = qs + 2; q <= qe; ++q) {
+            if (q + 2 <= qe) load_row(q + 2, nxt2);   // in flight while rows q, q + 1 are used
+            // ---- step A on row q - 1
+            const int ya = q - 1;
+            R d[9];
+            gather_pull(d, prev2, prev, cur);
+            R drho, jx, jy;
+            const CellSense<R> cs = cell_update<R, true, true>(d, rho0, inv_tau, drho, jx, jy);
+            const bool own_a = own_col && ya >= Yb && ya < Ye;
+            if (own_a) add_sums(acc_a, nfault, drho, jx, jy, cs);
+            if constexpr (TWO) {
+                R an[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) an[i] = Store<S>::to_real(Store<S>::from_real(d[i]));
+                // ---- step B on row q - 2 (step A rows q - 3, q - 2, q - 1)
+                if (q >= qs + 4) {
+                    R e[9];
+                    gather_pull(e, aprev2, aprev, an);
+                    R drho2, jx2, jy2;
+                    const CellSense<R> cs2 = cell_update<R, true, true>(e, rho0, inv_tau, drho2, jx2, jy2);
+                    if (own_col) {
+                        store_cell(q - 2, e, cs2);
+                        add_sums(acc_b, nfault, drho2, jx2, jy2, cs2);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    aprev2[i] = aprev[i];
+                    aprev[i] = an[i];
+                }
+            } else {
+                if (own_a) store_cell(ya, d, cs);
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                prev2[i] = prev[i];
+                prev[i] = cur[i];
+                cur[i] = nxt[i];
+                nxt[i] = nxt2[i];
+            }
+        }
+    }
+    block_sums(acc_a, part_a + (long long)blockIdx.x * kNsums);
+    if constexpr (TWO) {
+        __syncthreads();                          // block_sums' LDS is read before it is written again
+        block_sums(acc_b, part_b + (long long)blockIdx.x * kNsums);
+    }
+    if (nfault) atomicAdd(faults, (unsigned long long)nfault);
+}
+
+template <typename S>
+static hipError_t launch_two(const D2Q9Args& a, bool two, const void* fin, void* fout, void* sens,
+                             uint8_t* flags, double* part_a, double* part_b, unsigned long long* faults,
+                             hipStream_t st)
+{
+    using raw = typename Store<S>::raw;
+    using R = typename Store<S>::real;
+    const dim3 grid((unsigned)d2q9_two_blocks(sizeof(raw) == 8 ? 0 : 1, a.nx, a.ny)), block(kBlock);
+    if (two)
+        d2q9_fused2_kernel<S, true><<<grid, block, 0, st>>>(a, (const raw*)fin, (raw*)fout, (R*)sens, flags,
+                                                            part_a, part_b, faults);
+    else
+        d2q9_fused2_kernel<S, false><<<grid, block, 0, st>>>(a, (const raw*)fin, (raw*)fout, (R*)sens, flags,
+                                                             part_a, part_b, faults);
+    return hipGetLastError();
+}
+
+// Workgroups of the two-step launches: one wave per strip of kSweepW columns
+// and kSweepH rows.
+int d2q9_two_blocks(int dtype, int nx, int ny)
+{
+    (void)dtype;
+    const long long waves = (long long)((nx + kSweepW - 1) / kSweepW) * ((ny + kSweepH - 1) / kSweepH);
+    return (int)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+}
+
+hipError_t launch_d2q9_two(int dtype, const D2Q9Args& a, bool two, const void* fin, void* fout, void* sens,
+                           uint8_t* flags, double* part_a, double* part_b, unsigned long long* faults,
+                           hipStream_t s)
+{
+    switch (dtype) {
+    case 0: return launch_two<double>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
+    case 1: return launch_two<float>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
+    case 2: return launch_two<bf16_t>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
+    case 3: return launch_two<f16_t>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename S, int VEC>

@@ -97,7 +97,9 @@ const char* validate_config(const lks_config* c)
     if (c->model != LKS_MODEL_BGK && c->model != LKS_MODEL_DDF) return "model must be BGK or DDF";
     if (c->layout != LKS_LAYOUT_PLANES && c->layout != LKS_LAYOUT_ROWS) return "layout must be PLANES or ROWS";
     if (c->launch_nt < 0 || c->launch_nt > 2) return "launch_nt must be 0, 1 or 2";
-    if (c->launch_reserved != 0) return "launch_reserved must be 0";
+    if (c->launch_steps < 0 || c->launch_steps > 2) return "launch_steps must be 0, 1 or 2";
+    if (c->launch_steps == 2 && (c->lattice != LKS_D2Q9 || c->ext_mask))
+        return "launch_steps 2 needs D2Q9 without extension sensors";
     if (c->model == LKS_MODEL_DDF) {
         if (c->lattice != LKS_D2Q25) return "the double distribution needs D2Q25";
         if (!(c->gamma > 1.0 && c->gamma < 2.0)) return "gamma must be in (1, 2)";
@@ -166,7 +168,7 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
 int step_blocks(const lks_config& c)
 {
     if (c.lattice == LKS_D2Q25) return d2q25_args(c).nblocks;
-    int nb = 0;
+    int nb = c.launch_steps == 2 ? lks::d2q9_two_blocks(c.dtype, c.nx, c.ny) : 0;
     for (int vec : {1, 2, 4}) {
         const int b = d2q9_shape(c, vec).nblocks;
         nb = b > nb ? b : nb;
@@ -227,6 +229,7 @@ struct lks_ctx {
     lks::D2Q9Args a9;
     lks::D2Q25Args a25;
     int nblocks;
+    int nblocks2;          // workgroups of the two-step launches (launch_steps 2), else 0
     double* partials;
     unsigned long long* faults;
     std::string err;
@@ -339,10 +342,12 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     c->a25 = d2q25_args(*cfg);
     c->a25.aux = aux;
     c->nblocks = cfg->lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
+    c->nblocks2 = cfg->launch_steps == 2 ? lks::d2q9_two_blocks(cfg->dtype, cfg->nx, cfg->ny) : 0;
     // the partials area holds chunk_steps steps of the launch with the most
-    // workgroups; the launch chosen here may fit more steps per reduction
+    // workgroups; the launches chosen here may fit more steps per reduction
     {
-        const long long per_step = (long long)c->nblocks * lks::kNsumsHost * (long long)sizeof(double);
+        const int nbmax = c->nblocks2 > c->nblocks ? c->nblocks2 : c->nblocks;
+        const long long per_step = (long long)nbmax * lks::kNsumsHost * (long long)sizeof(double);
         long long k = (long long)partials_bytes(*cfg) / per_step;   // >= chunk_steps >= 1
         if (k > kMaxChunk) k = kMaxChunk;
         if (k > cfg->max_steps) k = cfg->max_steps;
@@ -397,11 +402,23 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
     if (c->cfg.ext_mask && !fused)
         return fail(c, LKS_EUNSUPPORTED, "extension sensors are computed by the fused step only");
     const lks::D2Q9Args& a = c->a9;
-    const int nb = c->nblocks;
+    const bool two = fused && c->nblocks2 > 0;
+    const int nb = two ? c->nblocks2 : c->nblocks;
     int done = 0;
     while (done < nsteps) {
         const int m = (nsteps - done) < c->chunk ? (nsteps - done) : c->chunk;
-        for (int s = 0; s < m; ++s) {
+        for (int s = 0; two && s < m;) {
+            // two steps per launch; an odd last step of the batch takes one
+            double* pa = c->partials + (size_t)s * nb * lks::kNsumsHost;
+            const bool pair = s + 1 < m;
+            hipError_t e = lks::launch_d2q9_two(c->cfg.dtype, a, pair, c->buf.pop[c->cur], c->buf.pop[1 - c->cur],
+                                                c->buf.sensors, c->buf.flags, pa,
+                                                pa + (size_t)nb * lks::kNsumsHost, c->faults, c->stream);
+            if (lks_status st = hip_check(c, e, "step kernel")) return st;
+            c->cur = 1 - c->cur;
+            s += pair ? 2 : 1;
+        }
+        for (int s = 0; !two && s < m; ++s) {
             double* part = c->partials + (size_t)s * nb * lks::kNsumsHost;
             void* f = c->buf.pop[c->cur];
             void* g = c->buf.pop[1 - c->cur];

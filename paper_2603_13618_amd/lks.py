@@ -69,7 +69,7 @@ class Config(ctypes.Structure):
                 ("model", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("thr_qe", ctypes.c_double * 2), ("launch_nt", ctypes.c_int32),
-                ("launch_reserved", ctypes.c_int32)]
+                ("launch_steps", ctypes.c_int32)]
 
 
 class Box(ctypes.Structure):
@@ -156,7 +156,7 @@ def _stream_handle(device):
 def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                 bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
                 launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
-                prandtl=0.71, thr_qe=None, layout=LAYOUT_PLANES, launch_nt=0):
+                prandtl=0.71, thr_qe=None, layout=LAYOUT_PLANES, launch_nt=0, launch_steps=0):
     c = Config()
     c.lattice, c.nx, c.ny = lattice, nx, ny
     c.dtype = DTYPES[dtype] if isinstance(dtype, str) else dtype
@@ -177,7 +177,7 @@ def make_config(lattice=D2Q9, nx=64, ny=64, dtype=F32, tau=0.6, mu=0.0, dt=0.0, 
         c.thr_ext[k][0], c.thr_ext[k][1] = float(te[k, 0]), float(te[k, 1])
     c.model = MODELS[model] if isinstance(model, str) else model
     c.layout = LAYOUTS[layout] if isinstance(layout, str) else layout
-    c.launch_nt, c.launch_reserved = launch_nt, 0
+    c.launch_nt, c.launch_steps = launch_nt, launch_steps
     c.gamma, c.prandtl = gamma, prandtl
     tq = (math.inf, math.inf) if thr_qe is None else tuple(float(v) for v in thr_qe)
     c.thr_qe[0], c.thr_qe[1] = tq
@@ -215,11 +215,12 @@ class Lattice:
     def __init__(self, lattice=D2Q9, nx=64, ny=64, dtype="f32", tau=0.6, mu=0.0, dt=0.0, dx=1.0,
                  bc=(PERIODIC, PERIODIC), rho0=1.0, thr=None, flag_mask=0, max_steps=1,
                  launch_rows=0, launch_vec=0, ext=None, thr_ext=None, model=MODEL_BGK, gamma=1.4,
-                 prandtl=0.71, thr_qe=None, layout=LAYOUT_ROWS, launch_nt=0, device="cuda"):
+                 prandtl=0.71, thr_qe=None, layout=LAYOUT_ROWS, launch_nt=0, launch_steps=0,
+                 device="cuda"):
         self.device = torch.device(device)
         self.cfg = make_config(lattice, nx, ny, dtype, tau, mu, dt, dx, bc, rho0, thr, flag_mask,
                                max_steps, launch_rows, launch_vec, ext, thr_ext, model, gamma,
-                               prandtl, thr_qe, layout, launch_nt)
+                               prandtl, thr_qe, layout, launch_nt, launch_steps)
         self.layout = self.cfg.layout
         self.model = self.cfg.model
         self.Q = 50 if self.model == MODEL_DDF else lattice

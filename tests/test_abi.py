@@ -59,7 +59,7 @@ def test_abi_struct_layout_matches_header(tmp_path):
     # of include/lks.h
     fields = ["lattice", "nx", "dtype", "tau", "rho0", "flag_mask", "launch_rows", "thr",
               "max_steps", "launch_vec", "ext_mask", "ext_reserved", "thr_ext", "model",
-              "layout", "gamma", "prandtl", "thr_qe", "launch_nt", "launch_reserved"]
+              "layout", "gamma", "prandtl", "thr_qe", "launch_nt", "launch_steps"]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"lks.h\"\nint main(void){\n"
                    + 'printf("%zu %zu", sizeof(lks_config), sizeof(lks_buffers));\n'
@@ -142,10 +142,15 @@ def test_population_layout_validation_on_host():
     # the store hint: 0 automatic, 1 plain, 2 non-temporal; nothing else
     for v in (0, 1, 2):
         assert lks.scratch_bytes(lks.make_config(9, 64, 48, "f32", tau=0.6, launch_nt=v)) > 0
-    for field, v in (("launch_nt", 3), ("launch_nt", -1), ("launch_reserved", 1)):
+    for field, v in (("launch_nt", 3), ("launch_nt", -1), ("launch_steps", 3), ("launch_steps", -1)):
         r = lks.make_config(9, 64, 48, "f32", tau=0.6)
         setattr(r, field, v)
         assert lks.scratch_bytes(r) == 0
+    # two steps per launch: D2Q9 without extension sensors only
+    assert lks.scratch_bytes(lks.make_config(9, 64, 48, "f32", tau=0.6, launch_steps=2)) > 0
+    assert lks.scratch_bytes(lks.make_config(9, 64, 48, "f32", tau=0.6, launch_steps=2, ext=["kn"])) == 0
+    assert lks.scratch_bytes(lks.make_config(25, 64, 48, "f32", mu=1e-3, dt=1e-3, dx=0.1,
+                                             launch_steps=2)) == 0
 
 
 @pytest.mark.parametrize("name", ["lks_step", "lks_moments", "lks_check", "lks_init_equilibrium"])

@@ -9,6 +9,7 @@ FP64 global sums, all in one kernel (plus one small reduction kernel per
 batch of steps).  Inputs are resident in HBM before the timed region starts.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--forms]
+                    [--ext] [--ddf] [--q25] [--regrid] [--two-step]
     python bench.py --mode kernel --steps 5      # short run for profilers
     python bench.py --mode copy                  # copy-kernel yardstick only
 
@@ -17,6 +18,7 @@ Prints ONE JSON line (the last line of stdout).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -63,6 +65,9 @@ def parse():
                    help="also time the D2Q25 double-distribution step on the 2048^2 Riemann problem")
     p.add_argument("--q25", action="store_true",
                    help="also time the D2Q25 single-distribution step on the 2048^2 Riemann problem")
+    p.add_argument("--two-step", action="store_true",
+                   help="also time two fused steps per launch (launch_steps = 2) against one, "
+                        "FP32 on the 4096^2 and 8192^2 smooth fields")
     p.add_argument("--regrid", action="store_true",
                    help="also time the regridding hand-off on the final flag map")
     p.add_argument("--layout", choices=["planes", "rows"], default="rows",
@@ -71,7 +76,8 @@ def parse():
     p.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench")
     p.add_argument("--workload", choices=["smooth4096", "riemann2048", "smooth8192-bf16",
                                           "smooth8192-f16", "adjoint1024", "smooth4096-ext",
-                                          "riemann2048-ext", "riemann2048-ddf", "riemann2048-ddf-ext"],
+                                          "riemann2048-ext", "riemann2048-ddf", "riemann2048-ddf-ext",
+                                          "smooth4096-two", "smooth8192-two"],
                    default="smooth4096", help="workload of --mode kernel (profiling runs)")
     p.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                    help="assemble the traffic summary from four rocprofv3 --pmc output "
@@ -309,6 +315,8 @@ def main():
         out["ddf"] = time_ddf(torch, lks, inputs, workloads, dev, ev)
     if args.q25:
         out["q25"] = time_q25(torch, lks, inputs, workloads, dev, ev)
+    if args.two_step:
+        out["two_step"] = time_two_step(torch, lks, inputs, workloads, dev, ev)
     if regrid is not None:
         out["regrid"] = regrid
 
@@ -518,6 +526,15 @@ def kernel_only(args, torch, lks, inputs, workloads, dev):
                           max_steps=max(args.steps, 1), layout=LAYOUT, device=dev)
         lat.init(rho, ux, uy, T)
         lat.step(args.steps)
+    elif args.workload.endswith("-two"):
+        wl = workloads.SMOOTH_4096 if args.workload.startswith("smooth4096") else workloads.SMOOTH_8192
+        n = wl["nx"]
+        rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+        lat = lks.Lattice(9, n, n, "f32", tau=wl["tau"], thr=wl["thr"] or workloads.SMOOTH_4096["thr"],
+                          flag_mask=wl["flag_mask"], max_steps=max(args.steps, 1), layout=LAYOUT,
+                          launch_steps=2, device=dev)
+        lat.init(rho, ux, uy)
+        lat.step(args.steps)
     elif args.workload.startswith("smooth8192"):
         wl = workloads.SMOOTH_8192
         n = wl["nx"]
@@ -539,6 +556,43 @@ def kernel_only(args, torch, lks, inputs, workloads, dev):
         L.backward()
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernel", "workload": args.workload, "steps": args.steps}))
+
+
+def time_two_step(torch, lks, inputs, workloads, dev, ev, k=32, rounds=5):
+    """Two fused steps per launch (launch_steps = 2) against one, FP32 on the
+    smooth 4096^2 and 8192^2 fields: each form warmed up, then timed in
+    alternating runs of k steps, best run of each."""
+    res = {}
+    for wl in (workloads.SMOOTH_4096, workloads.SMOOTH_8192):
+        n = wl["nx"]
+        rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+        lats = {}
+        for ls in (0, 2):
+            lat = lks.Lattice(9, n, n, "f32", tau=wl["tau"], thr=wl["thr"] or workloads.SMOOTH_4096["thr"],
+                              flag_mask=wl["flag_mask"], max_steps=64, layout=LAYOUT, launch_steps=ls,
+                              device=dev)
+            lat.init(rho, ux, uy)
+            lat.step(60)
+            lats[ls] = lat
+        torch.cuda.synchronize()
+        best = {0: math.inf, 2: math.inf}
+        for _ in range(rounds):
+            for ls, lat in lats.items():
+                s, e = ev(), ev()
+                s.record()
+                lat.step(k)
+                e.record()
+                torch.cuda.synchronize()
+                best[ls] = min(best[ls], s.elapsed_time(e) / k * 1e-3)
+        res[f"f32_{n}"] = {"grid": [n, n],
+                           "one_step": {"MLUPS": round(n * n / best[0] / 1e6, 1),
+                                        "us_per_step": round(best[0] * 1e6, 1)},
+                           "two_step": {"MLUPS": round(n * n / best[2] / 1e6, 1),
+                                        "us_per_step": round(best[2] * 1e6, 1)},
+                           "speedup": round(best[0] / best[2], 3)}
+        del lats, lat
+        torch.cuda.empty_cache()
+    return res
 
 
 def time_forms(torch, lks, inputs, workloads, dev, ev):

@@ -200,10 +200,12 @@ __device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
 
 // KL integrand phi(x) = (1+x) ln(1+x) - x, so that f ln(f/feq) - f + feq =
 // feq * phi(fneq/feq) = fneq * x * p(x) with x = fneq/feq and p(x) = phi(x)/x^2.
-// Multiply-adds here and in the kernels' sensor sums fuse only within one
-// source expression (fp contract on): fusion across statements depends on the
-// basic blocks around the inlined code, which differ between kernels, and the
-// sensors are to be the same bits in every kernel that computes them.
+// The FP64 multiply-adds here are explicit fma: left to contraction, whether
+// a multiply and an add fuse depends on the basic blocks around the inlined
+// code, which differ between kernels, and the sensors are to be the same bits
+// in every kernel that computes them.  (The FP32 series is left to
+// contraction: written as fma it costs the D2Q25 kernel 18 registers and a
+// wave per SIMD, and its bits agree between kernels as written.)
 // Near 0 the closed form cancels; there the Taylor series
 // p(x) = sum_{n>=2} (-1)^n x^(n-2) / (n(n-1)) is used for |x| <= KlCut:
 // truncated after n = 7 in FP32 (relative truncation 2 x^6/56 < 4e-8 at
@@ -214,7 +216,6 @@ template <> struct KlCut<double> { static constexpr double v = 0.01; };
 
 __device__ __forceinline__ float kl_series(float x)
 {
-#pragma clang fp contract(on)
     float p = -1.0f / 42.0f;
     p = p * x + 1.0f / 30.0f;
     p = p * x + -1.0f / 20.0f;
@@ -226,15 +227,14 @@ __device__ __forceinline__ float kl_series(float x)
 
 __device__ __forceinline__ double kl_series(double x)
 {
-#pragma clang fp contract(on)
     double p = -1.0 / 72.0;
-    p = p * x + 1.0 / 56.0;
-    p = p * x + -1.0 / 42.0;
-    p = p * x + 1.0 / 30.0;
-    p = p * x + -1.0 / 20.0;
-    p = p * x + 1.0 / 12.0;
-    p = p * x + -1.0 / 6.0;
-    p = p * x + 0.5;
+    p = fma(p, x, 1.0 / 56.0);
+    p = fma(p, x, -1.0 / 42.0);
+    p = fma(p, x, 1.0 / 30.0);
+    p = fma(p, x, -1.0 / 20.0);
+    p = fma(p, x, 1.0 / 12.0);
+    p = fma(p, x, -1.0 / 6.0);
+    p = fma(p, x, 0.5);
     return p;
 }
 
@@ -242,9 +242,8 @@ __device__ __forceinline__ double kl_series(double x)
 template <typename R>
 __device__ __forceinline__ R kl_phi(R x)
 {
-#pragma clang fp contract(on)
     if (fabs(x) <= KlCut<R>::v) return x * x * kl_series(x);
-    return (R(1) + x) * log1p_r(x) - x;
+    return fma(R(1) + x, log1p_r(x), -x);
 }
 
 // derivative phi'(x) = ln(1+x) (used by the adjoint seed)

@@ -603,7 +603,9 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
 // 62: the strip and a one-column ring), with the x neighbours from the
 // adjacent lanes (DPP wave shifts) and the y neighbours from the two previous
 // raw rows; its post-collision values, rounded to the storage type as a stored
-// state would be, feed step B on row q - 2 (lanes 2 to 61) in the same way.
+// state would be, feed step B in the same way.  Step B runs on row q - 3
+// (lanes 2 to 61) from step-A rows of earlier iterations, so the two cell
+// updates of an iteration are independent and their instructions interleave.
 // The strip's rows plus a two-row ring are read once; step B stores
 // populations, sensors and flags.  No LDS and no barrier until the final sums.
 // Each cell's sums and faults are counted by the wave that owns it, for both
@@ -739,43 +741,45 @@ __global__ __launch_bounds__(kBlock) void d2q9_fused2_kernel(
         // raw rows qs .. qe; step A on rows qs + 1 .. qe - 1, step B (TWO) on Yb .. Ye - 1
         const int qs = Yb - (TWO ? 2 : 1), qe = Ye + (TWO ? 1 : 0);
         R prev2[9], prev[9], cur[9], nxt[9] = {}, nxt2[9] = {};
-        R aprev2[9], aprev[9];
+        R aprev3[9], aprev2[9], aprev[9];
         load_row(qs, prev2);
         load_row(qs + 1, prev);
         load_row(qs + 2, cur);
         if (qs + 3 <= qe) load_row(qs + 3, nxt);
-        for (int q = qs + 2; q <= qe; ++q) {
-            if (q + 2 <= qe) load_row(q + 2, nxt2);   // in flight while rows q, q + 1 are used
-            // ---- step A on row q - 1
-            const int ya = q - 1;
-            R d[9];
-            gather_pull(d, prev2, prev, cur);
-            R drho, jx, jy;
-            const CellSense<R> cs = cell_update<R, true, true>(d, rho0, inv_tau, drho, jx, jy);
-            const bool own_a = own_col && ya >= Yb && ya < Ye;
-            if (own_a) add_sums(acc_a, nfault, drho, jx, jy, cs);
+        const int qend = qe + (TWO ? 1 : 0);
+        for (int q = qs + 2; q <= qend; ++q) {
+            if (q + 2 <= qe) load_row(q + 2, nxt2);
             if constexpr (TWO) {
-                R an[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) an[i] = Store<S>::to_real(Store<S>::from_real(d[i]));
-                // ---- step B on row q - 2 (step A rows q - 3, q - 2, q - 1)
-                if (q >= qs + 4) {
+                // ---- step B on row q - 3 (step A rows q - 4, q - 3, q - 2 of earlier iterations)
+                if (q >= qs + 5) {
                     R e[9];
-                    gather_pull(e, aprev2, aprev, an);
+                    gather_pull(e, aprev3, aprev2, aprev);
                     R drho2, jx2, jy2;
                     const CellSense<R> cs2 = cell_update<R, true, true>(e, rho0, inv_tau, drho2, jx2, jy2);
                     if (own_col) {
-                        store_cell(q - 2, e, cs2);
+                        store_cell(q - 3, e, cs2);
                         add_sums(acc_b, nfault, drho2, jx2, jy2, cs2);
                     }
                 }
+            }
+            if (q <= qe) {
+                const int ya = q - 1;
+                R d[9];
+                gather_pull(d, prev2, prev, cur);
+                R drho, jx, jy;
+                const CellSense<R> cs = cell_update<R, true, true>(d, rho0, inv_tau, drho, jx, jy);
+                const bool own_a = own_col && ya >= Yb && ya < Ye;
+                if (own_a) add_sums(acc_a, nfault, drho, jx, jy, cs);
+                if constexpr (TWO) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    aprev2[i] = aprev[i];
-                    aprev[i] = an[i];
+                    for (int i = 0; i < 9; ++i) {
+                        aprev3[i] = aprev2[i];
+                        aprev2[i] = aprev[i];
+                        aprev[i] = Store<S>::to_real(Store<S>::from_real(d[i]));
+                    }
+                } else {
+                    if (own_a) store_cell(ya, d, cs);
                 }
-            } else {
-                if (own_a) store_cell(ya, d, cs);
             }
 #pragma unroll
             for (int i = 0; i < 9; ++i) {

@@ -81,3 +81,28 @@ def test_two_step_counts_faults_of_both_steps(orc):
             _same(ref.state, lat.state, "state")
             _same(ref.flags, lat.flags, "flags")
     assert counts[0] == counts[1] > 0
+
+
+def test_two_step_bit_identical_past_2_31_elements():
+    """16384^2 FP32 (9 x 2^28 population elements per state): two steps per
+    launch against one, compared on the device."""
+    n = 16384
+    rho, ux, uy = inputs.smooth_random(n, seed=1, cutoff=8)
+    thr = np.array([[1e-6, 1e-5], [1e-3, 1e-2], [1e-3, 1e-2], [np.inf, np.inf]])
+    mask = lks.S_KL | lks.S_NEQ | lks.S_PI
+    lats = []
+    for ls in (0, 2):
+        lat = lks.Lattice(9, n, n, "f32", tau=0.52, thr=thr, flag_mask=mask, max_steps=2, launch_steps=ls)
+        lat.init(rho, ux, uy)
+        lat.step(2)
+        torch.cuda.synchronize()
+        lats.append(lat)
+    a, b = lats
+    assert torch.equal(a.state, b.state)
+    assert torch.equal(a.sensors, b.sensors)
+    assert torch.equal(a.flags, b.flags)
+    assert a.check() == b.check() == 0
+    sa, sb = a.sums.cpu().numpy(), b.sums.cpu().numpy()
+    scale = np.abs(sa)
+    scale[:, 1:3] += 0.2 * n * n
+    assert np.all(np.abs(sa - sb) <= 2.0 ** -21 * scale + 1e-300)

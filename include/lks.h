@@ -194,10 +194,12 @@ typedef struct {
     int32_t launch_steps; /* fused D2Q9 steps per launch: 0 or 1 one, 2 two
                              (temporal blocking: the state crosses HBM once
                              per two steps; D2Q9 without extension sensors;
-                             an odd last step runs alone).  A launch hint:
-                             the results are the same bits, but the state
-                             changes buffer once per launch, so lks_current
-                             names the buffer that holds it                 */
+                             an odd last step of a reduction batch runs
+                             alone; a batch holds at most max_steps steps,
+                             so max_steps = 1 runs one step per launch).
+                             A launch hint: the results are the same bits,
+                             but the state changes buffer once per launch,
+                             so lks_current names the buffer that holds it */
 } lks_config;
 
 typedef struct {

@@ -210,6 +210,9 @@ class Lattice:
     distribution with the quasi-equilibrium collision (gamma, prandtl; pop
     then holds 50 planes, f then g, and sensors 5 planes, the fifth S_QE with
     thresholds thr_qe and flag bit S_QE).
+    launch_steps: 2 runs two fused D2Q9 steps per launch (no extension
+    sensors; pairs need max_steps >= 2); the results are the same bits, and
+    `state` follows the buffer that holds the current state.
     """
 
     def __init__(self, lattice=D2Q9, nx=64, ny=64, dtype="f32", tau=0.6, mu=0.0, dt=0.0, dx=1.0,

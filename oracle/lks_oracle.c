@@ -35,7 +35,11 @@
  *   - extended sensors on demand (orc_ext_sensors): the rest of Table I on
  *     the f distribution -- Knudsen, relative H, H dissipation, KL
  *     dissipation, entropic estimate, rate of shear, viscous heating, Fourier
- *     flux (D2Q25), rate of compression and rate of strain (D2Q9);
+ *     flux (D2Q25), rate of compression and rate of strain (D2Q9).  The
+ *     entropic estimate is parity unpinned beyond leading order: the printed
+ *     polynomial (eqs. alpha-polynomial-1/2) has a first correction -4 times
+ *     that of the root of its defining condition (eq. H-mirr-equal), and is
+ *     evaluated as printed;
  *   - refinement flags (Sec. II.B.2, regridding step 1): per enabled sensor
  *     level = [s > theta1] + [s > theta2]; flag = max over sensors; a cell
  *     whose f_i or f^eq_i is not strictly positive (Sec. III.C, positivity
@@ -378,7 +382,9 @@ enum {
  * its defining condition (eq. H-mirr-equal): the exact root is
  * alpha = 2 - (1/3) sum f^neq^3/f^2 / sum f^neq^2/f + O(y^2), the polynomial's
  * first correction is -4 times that, and the higher terms differ in structure.
- * Pinned at leading order only; |2 - alpha_f| = 0 when a_1 = 0. */
+ * Parity unpinned beyond leading order: only the printed text fixes the
+ * r2^2, r3 and higher coefficients, and the paper is at odds with itself
+ * there.  |2 - alpha_f| = 0 when a_1 = 0. */
 static void cell_ext_sensors(const orc_rule* r, const double* f, const double* feq, int lattice,
                              double par, double* s)
 {

@@ -137,6 +137,11 @@ enum { LKS_MODEL_BGK = 0, LKS_MODEL_DDF = 1 };
  *   ALPHA     |2 - alpha_f|, the printed polynomial with f^neq = f - f^eq
  *                                                 Sec. III.B.6, eqs. sensor-alpha-kin,
  *                                                 alpha-polynomial-1/2
+ *             Parity unpinned beyond leading order: the printed polynomial's
+ *             first correction is -4 times that of the root of eq.
+ *             H-mirr-equal, so these values agree with the entropic estimate
+ *             in the limit f -> f^eq only (the sign and size of |2 - alpha|
+ *             beyond that follow the printed coefficients).
  *   SHEAR     |(1/mu)[(tr P / D) I - P]|_F        Sec. III.A.3, eq. sensor-S-kin
  *   QH        |u . P|                             Sec. III.A.5, eq. sensor-qH-kin
  *   QF        |q^neq - u . P|  (D2Q25 only)       Sec. III.A.7, eq. sensor-qF-kin-ryk (g = 0)

@@ -2,10 +2,10 @@
 // include/lks.h): validation, launch shapes, ping-pong bookkeeping, stream
 // handling and error reporting.  All device memory belongs to the caller.
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
-#include <string>
 
 #include "lks.h"
 #include "lks_internal.h"
@@ -15,8 +15,11 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kMaxChunk = 64;          // steps whose partial sums are reduced together
 constexpr size_t kHeader = 256;        // scratch: fault counter, padded
+constexpr size_t kErrLen = 512;        // bytes of an error message, NUL included
 
-thread_local std::string g_create_err;
+// message of the last failed call that had no context (lks_create,
+// lks_copy_probe), per host thread
+thread_local char g_err[kErrLen];
 
 int q_of(int lattice) { return lattice == LKS_D2Q9 ? 9 : (lattice == LKS_D2Q25 ? 25 : 0); }
 int nsens_of(int lattice) { return lattice == LKS_D2Q9 ? 3 : (lattice == LKS_D2Q25 ? 4 : 0); }
@@ -232,103 +235,93 @@ struct lks_ctx {
     int nblocks2;          // workgroups of the two-step launches (launch_steps 2), else 0
     double* partials;
     unsigned long long* faults;
-    std::string err;
+    char err[kErrLen];     // fixed storage: reporting an error allocates nothing
 };
 
 namespace {
 
-lks_status fail(lks_ctx* c, lks_status s, const std::string& msg)
+// printf-style message into the context (or the thread's context-free slot)
+__attribute__((format(printf, 3, 4))) lks_status fail(lks_ctx* c, lks_status s, const char* fmt, ...)
 {
-    if (c) c->err = msg;
-    else g_create_err = msg;
+    char* dst = c ? c->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(dst, kErrLen, fmt, ap);
+    va_end(ap);
     return s;
 }
 
 lks_status hip_check(lks_ctx* c, hipError_t e, const char* what)
 {
     if (e == hipSuccess) return LKS_OK;
-    return fail(c, LKS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return fail(c, LKS_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-} // namespace
-
-extern "C" {
-
-size_t lks_scratch_bytes(const lks_config* cfg)
+// Checks of a configuration and its buffers (the caller's scratch buffer
+// only when need_scratch).
+lks_status check_create(const lks_config* cfg, const lks_buffers* buf, bool need_scratch)
 {
-    if (validate_config(cfg)) return 0;
-    return scratch_for(*cfg);
-}
-
-int32_t lks_num_sensors(int32_t lattice) { return nsens_of(lattice); }
-
-int32_t lks_sensor_planes(const lks_config* cfg)
-{
-    if (validate_config(cfg)) return 0;
-    return planes_of(*cfg);
-}
-
-lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_stream, lks_ctx** out)
-{
-    if (!out) return fail(nullptr, LKS_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (const char* m = validate_config(cfg)) return fail(nullptr, LKS_EINVAL, m);
+    if (const char* m = validate_config(cfg)) return fail(nullptr, LKS_EINVAL, "%s", m);
     if (!buf) return fail(nullptr, LKS_EINVAL, "buffers are NULL");
     if (cfg->lattice == LKS_D2Q25 && cfg->dtype != LKS_F32 && cfg->dtype != LKS_F64)
         return fail(nullptr, LKS_EUNSUPPORTED, "D2Q25 supports F32 and F64 storage");
     if (cfg->ext_mask && cfg->dtype != LKS_F32 && cfg->dtype != LKS_F64)
         return fail(nullptr, LKS_EUNSUPPORTED, "extension sensors need F32 or F64 storage");
-    if (!buf->pop[0] || !buf->pop[1] || !buf->sensors || !buf->flags || !buf->sums || !buf->scratch)
+    if (!buf->pop[0] || !buf->pop[1] || !buf->sensors || !buf->flags || !buf->sums ||
+        (need_scratch && !buf->scratch))
         return fail(nullptr, LKS_EINVAL, "a buffer pointer is NULL");
     if (buf->pop[0] == buf->pop[1]) return fail(nullptr, LKS_EINVAL, "pop[0] and pop[1] alias");
-    const size_t need = scratch_for(*cfg);
-    if (buf->scratch_bytes < need)
-        return fail(nullptr, LKS_EINVAL,
-                    "scratch too small: need " + std::to_string(need) + " bytes");
-    if (!aligned(buf->scratch, 8) || !aligned(buf->sums, 8))
-        return fail(nullptr, LKS_EINVAL, "scratch and sums must be 8-byte aligned");
+    if (!aligned(buf->sums, 8)) return fail(nullptr, LKS_EINVAL, "sums must be 8-byte aligned");
     const size_t sb = store_bytes(cfg->dtype);
     if (!aligned(buf->pop[0], sb) || !aligned(buf->pop[1], sb) ||
         !aligned(buf->sensors, sens_bytes(cfg->dtype)))
         return fail(nullptr, LKS_EINVAL, "population or sensor buffer misaligned for its dtype");
+    return LKS_OK;
+}
 
-    lks_ctx* c = new (std::nothrow) lks_ctx();
-    if (!c) return fail(nullptr, LKS_EINVAL, "out of host memory");
-    c->cfg = *cfg;
-    c->buf = *buf;
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    c->Q = state_planes(*cfg);
-    c->nsens = planes_of(*cfg);
-    c->n = (long long)cfg->nx * cfg->ny;
+// Fill a context for a validated configuration.  scratch: device memory of
+// kHeader + `partials` + aux_bytes(cfg) bytes (fault counter, per-workgroup
+// partial sums of as many steps as `partials` bytes hold, up to kMaxChunk,
+// then the double distribution's hand-over).
+void setup_ctx(lks_ctx* c, const lks_config& cfg, const lks_buffers& buf, hipStream_t stream, char* scratch,
+               size_t partials)
+{
+    c->cfg = cfg;
+    c->buf = buf;
+    c->buf.scratch = scratch;
+    c->stream = stream;
+    c->Q = state_planes(cfg);
+    c->nsens = planes_of(cfg);
+    c->n = (long long)cfg.nx * cfg.ny;
     c->cur = 0;
     c->steps = 0;
     c->ready = false;
-    c->chunk = chunk_steps(*cfg);
-    c->faults = reinterpret_cast<unsigned long long*>(buf->scratch);
-    c->partials = reinterpret_cast<double*>(static_cast<char*>(buf->scratch) + kHeader);
-    void* aux = aux_bytes(*cfg) ? static_cast<char*>(buf->scratch) + kHeader + partials_bytes(*cfg) : nullptr;
+    c->faults = reinterpret_cast<unsigned long long*>(scratch);
+    c->partials = reinterpret_cast<double*>(scratch + kHeader);
+    void* aux = aux_bytes(cfg) ? scratch + kHeader + partials : nullptr;
 
     // widest vector the row length and buffer alignment allow (or the hint)
-    int vec = cfg->launch_vec > 0 ? cfg->launch_vec : wide_vec(cfg->dtype);
+    const size_t sb = store_bytes(cfg.dtype);
+    int vec = cfg.launch_vec > 0 ? cfg.launch_vec : wide_vec(cfg.dtype);
     const size_t vbytes = sb * vec;
-    if (cfg->nx % vec != 0 || !aligned(buf->pop[0], vbytes) || !aligned(buf->pop[1], vbytes) ||
-        !aligned(buf->sensors, sens_bytes(cfg->dtype) * vec) || !aligned(buf->flags, vec))
+    if (cfg.nx % vec != 0 || !aligned(buf.pop[0], vbytes) || !aligned(buf.pop[1], vbytes) ||
+        !aligned(buf.sensors, sens_bytes(cfg.dtype) * vec) || !aligned(buf.flags, vec))
         vec = 1;
     lks::D2Q9Args& a = c->a9;
-    a.nx = cfg->nx;
-    a.ny = cfg->ny;
+    a.nx = cfg.nx;
+    a.ny = cfg.ny;
     a.plane = c->n;
-    a.L = lks::pop_layout(cfg->layout, c->Q, cfg->nx, cfg->ny);
-    a.tau = cfg->tau;
-    a.rho0 = cfg->rho0;
-    std::memcpy(a.thr, cfg->thr, sizeof(a.thr));
-    a.mask = cfg->flag_mask;
-    a.g = d2q9_shape(*cfg, vec);
-    a.inv_tau_f = (float)(1.0 / cfg->tau);
-    a.rho0_f = (float)cfg->rho0;
+    a.L = lks::pop_layout(cfg.layout, c->Q, cfg.nx, cfg.ny);
+    a.tau = cfg.tau;
+    a.rho0 = cfg.rho0;
+    std::memcpy(a.thr, cfg.thr, sizeof(a.thr));
+    a.mask = cfg.flag_mask;
+    a.g = d2q9_shape(cfg, vec);
+    a.inv_tau_f = (float)(1.0 / cfg.tau);
+    a.rho0_f = (float)cfg.rho0;
     for (int s = 0; s < LKS_MAX_SENSORS; ++s)
-        for (int k = 0; k < 2; ++k) a.thr_f[s][k] = (float)cfg->thr[s][k];
-    a.x = ext_args(*cfg);
+        for (int k = 0; k < 2; ++k) a.thr_f[s][k] = (float)cfg.thr[s][k];
+    a.x = ext_args(cfg);
     // Non-temporal stores in the fused D2Q9 step when the two state buffers
     // exceed the 256 MB last-level cache: the next step's loads then come
     // from HBM either way and the hint keeps the stores from evicting the
@@ -336,64 +329,30 @@ lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_s
     // FP64 4096^2 5 %).  Below that size the states stay cache-resident
     // between steps, and the hint costs (BF16 2048^2 10 %, the 1024^2
     // adjoint 9 %).
-    a.nt_stores = cfg->launch_nt == 2 ? 1
-                : cfg->launch_nt == 1 ? 0
+    a.nt_stores = cfg.launch_nt == 2 ? 1
+                : cfg.launch_nt == 1 ? 0
                 : (2.0 * c->Q * (double)c->n * (double)sb > 256.0 * (1 << 20) ? 1 : 0);
-    c->a25 = d2q25_args(*cfg);
+    c->a25 = d2q25_args(cfg);
     c->a25.aux = aux;
-    c->nblocks = cfg->lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
-    c->nblocks2 = cfg->launch_steps == 2 ? lks::d2q9_two_blocks(cfg->dtype, cfg->nx, cfg->ny) : 0;
-    // the partials area holds chunk_steps steps of the launch with the most
-    // workgroups; the launches chosen here may fit more steps per reduction
-    {
-        const int nbmax = c->nblocks2 > c->nblocks ? c->nblocks2 : c->nblocks;
-        const long long per_step = (long long)nbmax * lks::kNsumsHost * (long long)sizeof(double);
-        long long k = (long long)partials_bytes(*cfg) / per_step;   // >= chunk_steps >= 1
-        if (k > kMaxChunk) k = kMaxChunk;
-        if (k > cfg->max_steps) k = cfg->max_steps;
-        c->chunk = (int)(k < 1 ? 1 : k);
-    }
-    *out = c;
-    return LKS_OK;
+    c->nblocks = cfg.lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
+    c->nblocks2 = cfg.launch_steps == 2 ? lks::d2q9_two_blocks(cfg.dtype, cfg.nx, cfg.ny) : 0;
+    // as many steps per reduction launch as the partials area holds for the
+    // launch with the most workgroups
+    const int nbmax = c->nblocks2 > c->nblocks ? c->nblocks2 : c->nblocks;
+    const long long per_step = (long long)nbmax * lks::kNsumsHost * (long long)sizeof(double);
+    long long k = (long long)partials / per_step;
+    if (k > kMaxChunk) k = kMaxChunk;
+    if (k > cfg.max_steps) k = cfg.max_steps;
+    // two steps per launch pair the steps of one reduction batch: an even
+    // batch leaves no step to the sweep kernel's one-step form but the odd
+    // last one of a call
+    if (cfg.launch_steps == 2 && k > 1) k &= ~1LL;
+    c->chunk = (int)(k < 1 ? 1 : k);
 }
 
-lks_status lks_init_equilibrium(lks_ctx* c, const double* rho, const double* ux, const double* uy,
-                                const double* T)
+// The step loop of lks_step (c valid).
+lks_status step_impl(lks_ctx* c, int32_t nsteps, int32_t fused)
 {
-    if (!c) return LKS_EINVAL;
-    if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
-    if (c->cfg.lattice == LKS_D2Q25 && !T) return fail(c, LKS_EINVAL, "T is required on D2Q25");
-    hipError_t e = ddf(c->cfg)
-                       ? lks::launch_d2q25_ddf_init(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0, cv_of(c->cfg),
-                                                    rho, ux, uy, T, c->buf.pop[0], c->stream)
-                   : c->cfg.lattice == LKS_D2Q25
-                       ? lks::launch_d2q25_init(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0, rho, ux, uy, T,
-                                                c->buf.pop[0], c->stream)
-                       : lks::launch_d2q9_init(c->cfg.dtype, c->n, c->a9.L, c->cfg.rho0, rho, ux, uy,
-                                               c->buf.pop[0], c->stream);
-    if (lks_status s = hip_check(c, e, "init kernel")) return s;
-    if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
-    c->cur = 0;
-    c->steps = 0;
-    c->ready = true;
-    return LKS_OK;
-}
-
-lks_status lks_restore(lks_ctx* c, int32_t pop_index, int64_t steps_done)
-{
-    if (!c) return LKS_EINVAL;
-    if (pop_index != 0 && pop_index != 1) return fail(c, LKS_EINVAL, "pop_index must be 0 or 1");
-    if (steps_done < 0) return fail(c, LKS_EINVAL, "steps_done must be >= 0");
-    if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
-    c->cur = pop_index;
-    c->steps = steps_done;
-    c->ready = true;
-    return LKS_OK;
-}
-
-lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
-{
-    if (!c) return LKS_EINVAL;
     if (nsteps < 0) return fail(c, LKS_EINVAL, "nsteps must be >= 0");
     if (fused != 0 && fused != 1) return fail(c, LKS_EINVAL, "fused must be 0 or 1");
     if (!c->ready) return fail(c, LKS_ESTATE, "step before init_equilibrium or restore");
@@ -456,6 +415,81 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
     return LKS_OK;
 }
 
+
+} // namespace
+
+extern "C" {
+
+size_t lks_scratch_bytes(const lks_config* cfg)
+{
+    if (validate_config(cfg)) return 0;
+    return scratch_for(*cfg);
+}
+
+int32_t lks_num_sensors(int32_t lattice) { return nsens_of(lattice); }
+
+int32_t lks_sensor_planes(const lks_config* cfg)
+{
+    if (validate_config(cfg)) return 0;
+    return planes_of(*cfg);
+}
+
+lks_status lks_create(const lks_config* cfg, const lks_buffers* buf, void* hip_stream, lks_ctx** out)
+{
+    if (!out) return fail(nullptr, LKS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (lks_status st = check_create(cfg, buf, true)) return st;
+    const size_t need = scratch_for(*cfg);
+    if (buf->scratch_bytes < need) return fail(nullptr, LKS_EINVAL, "scratch too small: need %zu bytes", need);
+    if (!aligned(buf->scratch, 8)) return fail(nullptr, LKS_EINVAL, "scratch must be 8-byte aligned");
+    lks_ctx* c = new (std::nothrow) lks_ctx();
+    if (!c) return fail(nullptr, LKS_EINVAL, "out of host memory");
+    setup_ctx(c, *cfg, *buf, static_cast<hipStream_t>(hip_stream), static_cast<char*>(buf->scratch),
+              partials_bytes(*cfg));
+    *out = c;
+    return LKS_OK;
+}
+
+lks_status lks_init_equilibrium(lks_ctx* c, const double* rho, const double* ux, const double* uy,
+                                const double* T)
+{
+    if (!c) return LKS_EINVAL;
+    if (!rho || !ux || !uy) return fail(c, LKS_EINVAL, "rho, ux and uy are required");
+    if (c->cfg.lattice == LKS_D2Q25 && !T) return fail(c, LKS_EINVAL, "T is required on D2Q25");
+    hipError_t e = ddf(c->cfg)
+                       ? lks::launch_d2q25_ddf_init(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0, cv_of(c->cfg),
+                                                    rho, ux, uy, T, c->buf.pop[0], c->stream)
+                   : c->cfg.lattice == LKS_D2Q25
+                       ? lks::launch_d2q25_init(c->cfg.dtype, c->n, c->a25.L, c->cfg.rho0, rho, ux, uy, T,
+                                                c->buf.pop[0], c->stream)
+                       : lks::launch_d2q9_init(c->cfg.dtype, c->n, c->a9.L, c->cfg.rho0, rho, ux, uy,
+                                               c->buf.pop[0], c->stream);
+    if (lks_status s = hip_check(c, e, "init kernel")) return s;
+    if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
+    c->cur = 0;
+    c->steps = 0;
+    c->ready = true;
+    return LKS_OK;
+}
+
+lks_status lks_restore(lks_ctx* c, int32_t pop_index, int64_t steps_done)
+{
+    if (!c) return LKS_EINVAL;
+    if (pop_index != 0 && pop_index != 1) return fail(c, LKS_EINVAL, "pop_index must be 0 or 1");
+    if (steps_done < 0) return fail(c, LKS_EINVAL, "steps_done must be >= 0");
+    if (lks_status s = hip_check(c, lks::launch_zero(c->faults, 1, c->stream), "zero kernel")) return s;
+    c->cur = pop_index;
+    c->steps = steps_done;
+    c->ready = true;
+    return LKS_OK;
+}
+
+lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
+{
+    if (!c) return LKS_EINVAL;
+    return step_impl(c, nsteps, fused);
+}
+
 lks_status lks_current(const lks_ctx* c, int32_t* pop_index, int64_t* steps_done)
 {
     if (!c) return LKS_EINVAL;
@@ -494,8 +528,7 @@ lks_status lks_read_host(lks_ctx* c, int32_t what, void* dst, size_t bytes)
     case 3: src = c->buf.sums; size = (size_t)c->cfg.max_steps * LKS_NSUMS * sizeof(double); break;
     default: return fail(c, LKS_EINVAL, "what must be 0..3");
     }
-    if (bytes != size)
-        return fail(c, LKS_EINVAL, "bytes must be " + std::to_string(size));
+    if (bytes != size) return fail(c, LKS_EINVAL, "bytes must be %zu", size);
     if (lks_status s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync")) return s;
     return hip_check(c, hipMemcpy(dst, src, size, hipMemcpyDeviceToHost), "copy to host");
 }
@@ -511,17 +544,21 @@ lks_status lks_check(lks_ctx* c, int64_t* n_nonpos)
     if (n_nonpos) *n_nonpos = (int64_t)nf;
     const long long rows = c->steps < c->cfg.max_steps ? c->steps : c->cfg.max_steps;
     if (rows > 0) {
-        std::string host((size_t)rows * LKS_NSUMS * sizeof(double), '\0');
-        if (lks_status s = hip_check(c, hipMemcpy(&host[0], c->buf.sums, host.size(),
-                                                  hipMemcpyDeviceToHost), "read sums"))
-            return s;
-        const double* h = reinterpret_cast<const double*>(host.data());
-        for (long long r = 0; r < rows; ++r)
-            for (int k = 0; k < 3; ++k)
-                if (std::isnan(h[r * LKS_NSUMS + k]))
-                    return fail(c, LKS_ENAN, "a mass or momentum sum is NaN");
+        // in pieces through a small host buffer
+        double h[64 * LKS_NSUMS];
+        for (long long r0 = 0; r0 < rows; r0 += 64) {
+            const long long nr = rows - r0 < 64 ? rows - r0 : 64;
+            if (lks_status s = hip_check(c, hipMemcpy(h, c->buf.sums + r0 * LKS_NSUMS,
+                                                      (size_t)nr * LKS_NSUMS * sizeof(double),
+                                                      hipMemcpyDeviceToHost), "read sums"))
+                return s;
+            for (long long r = 0; r < nr; ++r)
+                for (int k = 0; k < 3; ++k)
+                    if (std::isnan(h[r * LKS_NSUMS + k]))
+                        return fail(c, LKS_ENAN, "a mass or momentum sum is NaN");
+        }
     }
-    if (nf > 0) return fail(c, LKS_ENONPOS, std::to_string(nf) + " positivity-fault cells");
+    if (nf > 0) return fail(c, LKS_ENONPOS, "%llu positivity-fault cells", nf);
     return LKS_OK;
 }
 
@@ -659,7 +696,7 @@ const char* lks_status_str(lks_status s)
     return "unknown status";
 }
 
-const char* lks_last_error(const lks_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+const char* lks_last_error(const lks_ctx* c) { return c ? c->err : g_err; }
 
 lks_status lks_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream)
 {

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from oracle import torch_ref
-from paper_2603_13618_amd import adjoint, inputs
+from paper_2603_13618_amd import adjoint, inputs, lks
 
 from gpu_util import to_f64
 
@@ -77,3 +77,53 @@ def test_differentiation_workload_32_against_finite_differences(orc):
             worst32 = max(worst32, abs(fd - g32) / scale)
     print(f"FD vs adjoint: FP64 {worst:.2e}, FP32 {worst32:.2e}", flush=True)
     assert worst <= 1e-3 and worst32 <= 1e-3
+
+
+def _one_step_case(nx=24, ny=20, tau=0.6):
+    # a non-equilibrium state f_{n-1}, the pre-collision g_n = S f_{n-1} and
+    # random directions v, w (all FP64)
+    rho, ux, uy = inputs.random_state((ny, nx), 5, (0.9, 1.1), 0.08)
+    rng = np.random.default_rng(7)
+    f_prev = torch_ref.feq(*(torch.tensor(a) for a in (rho, ux, uy)))
+    f_prev = f_prev * (1.0 + 0.05 * torch.tensor(rng.standard_normal(f_prev.shape)))
+    v = torch.tensor(rng.standard_normal(f_prev.shape))
+    w = torch.tensor(rng.standard_normal(f_prev.shape))
+    lat = lks.Lattice(9, nx, ny, "f64", tau=tau)
+    w9 = torch.tensor([torch_ref._W[i] for i in range(9)], dtype=torch.float64)
+    prev = lat.new_state()
+    prev.copy_((f_prev - w9[:, None, None]).to(prev.device))       # deviation storage, rho0 = 1
+    return lat, f_prev, torch_ref.stream(f_prev), v, w, prev
+
+
+def test_fp64_adjoint_step_dot_product_identity():
+    # <J v, w> = <v, J^T w> for one step g_n -> g_{n+1} = S C(g_n): the forward
+    # derivative of the FP64 torch reference against the library's reverse step
+    tau = 0.6
+    lat, _, g, v, w, prev = _one_step_case(tau=tau)
+
+    def one_step(gg):
+        return torch_ref.stream(gg - (gg - torch_ref.feq(*torch_ref.macros(gg))) / tau)
+
+    _, jv = torch.func.jvp(one_step, (g,), (v,))
+    lhs = float((jv * w).sum())
+    lam_in, lam_out = lat.new_state(), lat.new_state()
+    lam_in.copy_(w.to(lam_in.device))
+    lat.adjoint_step(prev, lam_in, lam_out)
+    jtw = lam_out.cpu()
+    rhs = float((v * jtw).sum())
+    scale = float((v * jtw).abs().sum())
+    print(f"<Jv,w> {lhs:.15e} <v,J^T w> {rhs:.15e} rel {abs(lhs - rhs) / scale:.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+def test_fp64_adjoint_seed_is_the_kl_gradient():
+    # <dS/dg, v> of the summed smooth KL sensor at g_N = S f_{N-1}
+    lat, _, g, v, _, prev = _one_step_case()
+    _, dl = torch.func.jvp(lambda gg: torch_ref.kl(gg).sum(), (g,), (v,))
+    lam = lat.new_state()
+    lat.adjoint_seed_kl(prev, lam)
+    got = lam.cpu()
+    rhs = float((v * got).sum())
+    scale = float((v * got).abs().sum())
+    print(f"dL.v {float(dl):.15e} <v, seed> {rhs:.15e}", flush=True)
+    assert abs(float(dl) - rhs) <= 1e-12 * scale

@@ -72,27 +72,61 @@ def test_smooth_4096_fp32_fused_100_steps(orc):
     assert np.abs(s[:, 0] - rho.sum()).max() / rho.sum() < 1e-6
 
 
+# Errors of the 500-step 8192^2 run against the FP64 oracle, per storage type,
+# max over the sampled patches: density max |d rho| / rho0, velocity
+# max |d u| / max |u| (vector), each sensor max |d s| / max |s| of the patch,
+# the fraction of patch cells whose flag equals the oracle's, and the drift of
+# the FP64 total mass over the run, |M_500 - M_1| / M_1.  The bars are about
+# 1.5 times the measured values: regression bars, not accuracy claims (the
+# reduced-precision form has no accuracy target; 16-bit deviations cannot
+# resolve f^neq on this field, see the BF16 figures).
+C4_BARS = {
+    #        rho     u       S_KL    S_NEQ   S_PI    min flag agreement  mass drift
+    "bf16": (1.5e-3, 1.8e-2, 7.0,    2.2,    2.2,    0.35,               1e-6),
+    "f16": (1.8e-4, 2.5e-3, 0.5,    0.33,   0.3,    0.99,               1e-6),
+    "f32": (1e-7,   2e-6,   3e-4,   1.8e-4, 1.6e-4, 1.0,                1e-7),
+}
+C4_PATCHES = ((4000, 3000), (0, 0), (8192 - P, 8192 - 7 - P))
+
+
 def test_reduced_precision_8192_500_steps_report(orc):
     """BF16 and FP16 deviation storage (FP32 arithmetic, FP64 sums) on the
-    8192^2 smooth field: errors against the FP64 oracle are reported; the
-    asserted bounds only catch breakage (parity unpinned: no bar exists)."""
+    8192^2 smooth field, 500 steps: errors against the FP64 oracle on three
+    sampled patches, printed as a table and held to regression bars."""
     wl = workloads.SMOOTH_8192
     n, steps, tau = wl["nx"], wl["steps"], wl["tau"]
     thr, mask = np.asarray(workloads.SMOOTH_4096["thr"]), wl["flag_mask"]
-    x0, y0 = 4000, 3000
-    ref = _d2q9_window(orc, n, x0, y0, steps, tau, thr, mask)
+    refs = {p: _d2q9_window(orc, n, p[0], p[1], steps, tau, thr, mask) for p in C4_PATCHES}
     rho, ux, uy = inputs.smooth_random(n, seed=0, cutoff=16)
     for dtype in ("bf16", "f16", "f32"):
         lat = lks.Lattice(9, n, n, dtype, tau=tau, thr=thr, flag_mask=mask, max_steps=steps)
         lat.init(rho, ux, uy)
         lat.step(steps)
         torch.cuda.synchronize()
-        e_rho, e_u, es = _errs(lat, ref, y0, x0, 3)
-        agree = float((_patch(lat.flags, y0, x0) == ref["flags"]).mean())
-        print(f"{dtype}: rho {e_rho:.2e} u {e_u:.2e} sensors "
-              + " ".join(f"{e:.2e}" for e in es) + f" flag agreement {agree:.3f}", flush=True)
         assert lat.check() == 0
-        assert e_rho < 1e-2 and e_u < 0.2
+        worst = np.zeros(7)
+        worst[5] = 1.0
+        for (x0, y0), ref in refs.items():
+            e_rho, e_u, es = _errs(lat, ref, y0, x0, 3)
+            agree = float((_patch(lat.flags, y0, x0) == ref["flags"]).mean())
+            print(f"C4 {dtype} patch ({x0},{y0}): rho {e_rho:.2e} u {e_u:.2e} sensors "
+                  + " ".join(f"{e:.2e}" for e in es) + f" flag agreement {agree:.4f}", flush=True)
+            worst[:5] = np.maximum(worst[:5], [e_rho, e_u] + es)
+            worst[5] = min(worst[5], agree)
+        s = to_f64(lat.sums)
+        worst[6] = abs(s[-1, 0] - s[0, 0]) / s[0, 0]
+        print(f"C4 {dtype} worst: rho {worst[0]:.2e} u {worst[1]:.2e} sensors {worst[2]:.2e} "
+              f"{worst[3]:.2e} {worst[4]:.2e} flag agreement {worst[5]:.4f} mass drift {worst[6]:.2e}",
+              flush=True)
+        bars = C4_BARS[dtype]
+        assert all(worst[k] <= bars[k] for k in (0, 1, 2, 3, 4, 6)), (dtype, worst, bars)
+        assert worst[5] >= bars[5], (dtype, worst[5])
+        if dtype == "f32":
+            for (x0, y0), ref in refs.items():
+                _, _, es = _errs(lat, ref, y0, x0, 3)
+                bad, _ = flags_outside_band(_patch(lat.flags, y0, x0), ref["flags"], ref["sens"], thr,
+                                            mask, [max(e, 1e-6) for e in es] + [0])
+                assert bad == 0
         del lat
         torch.cuda.empty_cache()
 

@@ -255,6 +255,36 @@ lks_status lks_restore(lks_ctx* ctx, int32_t pop_index, int64_t steps_done);
  * sensors and flags hold the last step's values. */
 lks_status lks_step(lks_ctx* ctx, int32_t nsteps, int32_t fused);
 
+/* ---- Stepping without allocation ----
+ * For callers that cannot allocate memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Does what
+ * lks_restore(pop_index, steps_done) and then lks_step(nsteps, fused) do on a
+ * context created from cfg and buf, without creating one: no host or device
+ * memory is allocated.  cfg and buf are checked as by lks_create, except that
+ * buf->scratch must be NULL and buf->scratch_bytes 0: the kernels' scratch
+ * (fault counter, per-workgroup FP64 partial sums and, with LKS_MODEL_DDF,
+ * the per-cell hand-over between the step's two kernels) is a device array
+ * of LKS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (its address is looked up on the first call on a
+ * device, with that device current).  A configuration whose scratch does not
+ * fit (the hand-over plus one step's partial sums plus 256 bytes exceed the
+ * array) returns LKS_EINVAL before anything is launched; the message (as for
+ * lks_create, lks_last_error(NULL)) gives the bytes it needs.
+ * The work is enqueued on hip_stream (a hipStream_t of the current device)
+ * and the call returns without waiting.  *pop_index_out receives the index of
+ * the buffer that holds the state after the call.  Populations, sensors,
+ * flags and sums (step k of the call writes row (steps_done + k - 1) mod
+ * max_steps) are those lks_step writes, bit for bit.  The positivity-fault
+ * count is not reported (flag bit 7 marks the cells).
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (the fault counter is cleared at the start of each call):
+ * calls that overlap on one GPU, from other streams or host threads, race on
+ * it and must not be issued. */
+#define LKS_NOALLOC_SCRATCH_BYTES (16u << 20)
+lks_status lks_step_noalloc(const lks_config* cfg, const lks_buffers* buf, void* hip_stream,
+                            int32_t pop_index, int64_t steps_done, int32_t nsteps, int32_t fused,
+                            int32_t* pop_index_out);
+
 /* One fused step from the state src into dst (both Q*ny*nx values in the
  * context's layout and dtype, distinct, neither need be pop[0]/pop[1]); sensors and
  * flags receive this step's values, the sums buffer and the step count are

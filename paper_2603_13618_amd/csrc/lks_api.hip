@@ -1,10 +1,12 @@
 // lks_api.hip -- the extern "C" surface of liblks.so (declared in
 // include/lks.h): validation, launch shapes, ping-pong bookkeeping, stream
 // handling and error reporting.  All device memory belongs to the caller.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "lks.h"
@@ -18,7 +20,7 @@ constexpr size_t kHeader = 256;        // scratch: fault counter, padded
 constexpr size_t kErrLen = 512;        // bytes of an error message, NUL included
 
 // message of the last failed call that had no context (lks_create,
-// lks_copy_probe), per host thread
+// lks_step_noalloc, lks_copy_probe), per host thread
 thread_local char g_err[kErrLen];
 
 int q_of(int lattice) { return lattice == LKS_D2Q9 ? 9 : (lattice == LKS_D2Q25 ? 25 : 0); }
@@ -257,8 +259,8 @@ lks_status hip_check(lks_ctx* c, hipError_t e, const char* what)
     return fail(c, LKS_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Checks of a configuration and its buffers (the caller's scratch buffer
-// only when need_scratch).
+// Checks shared by lks_create and lks_step_noalloc (the caller's scratch
+// buffer is checked by lks_create only).
 lks_status check_create(const lks_config* cfg, const lks_buffers* buf, bool need_scratch)
 {
     if (const char* m = validate_config(cfg)) return fail(nullptr, LKS_EINVAL, "%s", m);
@@ -350,7 +352,7 @@ void setup_ctx(lks_ctx* c, const lks_config& cfg, const lks_buffers& buf, hipStr
     c->chunk = (int)(k < 1 ? 1 : k);
 }
 
-// The step loop of lks_step (c valid).
+// The step loop of lks_step and lks_step_noalloc (c valid).
 lks_status step_impl(lks_ctx* c, int32_t nsteps, int32_t fused)
 {
     if (nsteps < 0) return fail(c, LKS_EINVAL, "nsteps must be >= 0");
@@ -415,6 +417,45 @@ lks_status step_impl(lks_ctx* c, int32_t nsteps, int32_t fused)
     return LKS_OK;
 }
 
+
+constexpr int kMaxDevices = 64;
+
+} // namespace
+
+// Device scratch of lks_step_noalloc: the fault counter, the per-workgroup
+// FP64 partial sums and, for the double distribution, the per-cell hand-over.
+// One copy per GPU, held until the process ends.  In host code this name is
+// only a handle for hipGetSymbolAddress: kernels and copies take the device
+// address that call returns.
+static __device__ __align__(256) unsigned char scratch[LKS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// the address of `scratch` on each device, looked up once per device with
+// that device current
+std::atomic<void*> g_scratch_dev[kMaxDevices];
+std::mutex g_scratch_mu;
+
+lks_status noalloc_scratch(void** out)
+{
+    int dev = -1;
+    if (lks_status s = hip_check(nullptr, hipGetDevice(&dev), "hipGetDevice")) return s;
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, LKS_EUNSUPPORTED, "device index %d out of range", dev);
+    void* p = g_scratch_dev[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_dev[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            if (lks_status s = hip_check(nullptr, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                                         "hipGetSymbolAddress(scratch)"))
+                return s;
+            if (!p) return fail(nullptr, LKS_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+            g_scratch_dev[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return LKS_OK;
+}
 
 } // namespace
 
@@ -488,6 +529,44 @@ lks_status lks_step(lks_ctx* c, int32_t nsteps, int32_t fused)
 {
     if (!c) return LKS_EINVAL;
     return step_impl(c, nsteps, fused);
+}
+
+lks_status lks_step_noalloc(const lks_config* cfg, const lks_buffers* buf, void* hip_stream, int32_t pop_index,
+                            int64_t steps_done, int32_t nsteps, int32_t fused, int32_t* pop_index_out)
+{
+    if (!pop_index_out) return fail(nullptr, LKS_EINVAL, "pop_index_out is NULL");
+    if (lks_status st = check_create(cfg, buf, false)) return st;
+    if (buf->scratch || buf->scratch_bytes)
+        return fail(nullptr, LKS_EINVAL, "scratch must be NULL and scratch_bytes 0 (the library's array is used)");
+    if (pop_index != 0 && pop_index != 1) return fail(nullptr, LKS_EINVAL, "pop_index must be 0 or 1");
+    if (steps_done < 0) return fail(nullptr, LKS_EINVAL, "steps_done must be >= 0");
+    if (nsteps < 0) return fail(nullptr, LKS_EINVAL, "nsteps must be >= 0");
+    if (fused != 0 && fused != 1) return fail(nullptr, LKS_EINVAL, "fused must be 0 or 1");
+    // the partial sums of at least one step, behind the header, before the hand-over
+    const size_t aux = aux_bytes(*cfg);
+    const size_t room = (size_t)LKS_NOALLOC_SCRATCH_BYTES - kHeader;
+    const size_t one = (size_t)step_blocks(*cfg) * lks::kNsumsHost * sizeof(double);
+    if (aux > room || room - aux < one)
+        return fail(nullptr, LKS_EINVAL, "configuration needs %zu bytes of scratch, more than the %u the "
+                    "library holds per device", kHeader + one + aux, (unsigned)LKS_NOALLOC_SCRATCH_BYTES);
+    const size_t partials = (room - aux) / 256 * 256;
+    void* base = nullptr;
+    if (lks_status st = noalloc_scratch(&base)) return st;
+
+    lks_ctx c{};
+    setup_ctx(&c, *cfg, *buf, static_cast<hipStream_t>(hip_stream), static_cast<char*>(base), partials);
+    // as lks_restore: the state in pop[pop_index] after steps_done steps, faults cleared
+    c.cur = pop_index;
+    c.steps = steps_done;
+    c.ready = true;
+    lks_status st = hip_check(&c, lks::launch_zero(c.faults, 1, c.stream), "zero kernel");
+    if (st == LKS_OK) st = step_impl(&c, nsteps, fused);
+    if (st != LKS_OK) {
+        std::memcpy(g_err, c.err, kErrLen);
+        return st;
+    }
+    *pop_index_out = c.cur;
+    return LKS_OK;
 }
 
 lks_status lks_current(const lks_ctx* c, int32_t* pop_index, int64_t* steps_done)

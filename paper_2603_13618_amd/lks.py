@@ -111,6 +111,8 @@ def lib():
             "lks_restore": ([P, I32, I64], I32),
             "lks_step": ([P, I32, I32], I32),
             "lks_step_from": ([P, P, P], I32),
+            "lks_step_noalloc": ([ctypes.POINTER(Config), ctypes.POINTER(Buffers), P, I32, I64, I32, I32,
+                                  ctypes.POINTER(I32)], I32),
             "lks_current": ([P, ctypes.POINTER(I32), ctypes.POINTER(I64)], I32),
             "lks_moments": ([P, P, P, P, P], I32),
             "lks_read_host": ([P, I32, P, ctypes.c_size_t], I32),
@@ -409,6 +411,26 @@ def cluster(counts, nx, ny, ts, eff=0.98, min_tiles=1, max_boxes=None):
         raise LksError(st, f"lks_cluster needs {n.value} boxes (room for {max_boxes})"
                        if n.value > max_boxes else "invalid clustering arguments")
     return [(b.x0, b.y0, b.x1, b.y1) for b in boxes[: n.value]]
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20      # LKS_NOALLOC_SCRATCH_BYTES
+
+
+def step_noalloc(cfg, pop, sensors, flags, sums, pop_index=0, steps_done=0, nsteps=1, fused=True):
+    """lks_step_noalloc: nsteps steps of the state in pop[pop_index] (a state
+    reached after steps_done steps) with the library's own device scratch,
+    on torch's current stream; pop is a pair of state tensors, sensors, flags
+    and sums as a Lattice of cfg holds them.  Returns the index of the buffer
+    that holds the new state."""
+    buf = Buffers()
+    buf.pop[0], buf.pop[1] = pop[0].data_ptr(), pop[1].data_ptr()
+    buf.sensors, buf.flags, buf.sums = sensors.data_ptr(), flags.data_ptr(), sums.data_ptr()
+    buf.scratch, buf.scratch_bytes = None, 0
+    out = ctypes.c_int32(-1)
+    _check(lib().lks_step_noalloc(ctypes.byref(cfg), ctypes.byref(buf), _stream_handle(pop[0].device),
+                                  int(pop_index), int(steps_done), int(nsteps), 1 if fused else 0,
+                                  ctypes.byref(out)))
+    return out.value
 
 
 def copy_probe(dst, src):

@@ -54,6 +54,33 @@ def test_config_validation_on_host():
     assert L.lks_status_str(4) == b"non-positive populations"
 
 
+def test_step_noalloc_validates_on_host():
+    # every rejection happens before the device is touched
+    L = lks.lib()
+    fake = [ctypes.c_void_p(0x10000 * (k + 1)) for k in range(5)]
+
+    def call(cfg, scratch=None, out=True, pop_index=0, nsteps=1):
+        buf = lks.Buffers()
+        buf.pop[0], buf.pop[1] = fake[0].value, fake[1].value
+        buf.sensors, buf.flags, buf.sums = fake[2].value, fake[3].value, fake[4].value
+        buf.scratch, buf.scratch_bytes = scratch, (256 if scratch else 0)
+        res = ctypes.c_int32(-1)
+        return L.lks_step_noalloc(ctypes.byref(cfg), ctypes.byref(buf), None, pop_index, 0, nsteps, 1,
+                                  ctypes.byref(res) if out else None)
+
+    ok = lks.make_config(9, 64, 64, "f32", tau=0.6, max_steps=4)
+    assert call(ok, out=False) == 1
+    assert call(ok, scratch=0x20000) == 1 and b"scratch" in L.lks_last_error(None)
+    assert call(ok, pop_index=2) == 1
+    assert call(ok, nsteps=-1) == 1
+    assert call(lks.make_config(9, 64, 64, "f32", tau=0.5)) == 1
+    # one step's partial sums of a 65536^2 grid (128 MB) exceed the 16 MB array
+    big = lks.make_config(9, 65536, 65536, "f32", tau=0.6, layout=lks.LAYOUT_ROWS)
+    assert call(big) == 1
+    msg = L.lks_last_error(None).decode()
+    assert "scratch" in msg and str(lks.NOALLOC_SCRATCH_BYTES) in msg
+
+
 def test_abi_struct_layout_matches_header(tmp_path):
     # sizes and offsets of the ctypes mirror against what the C compiler makes
     # of include/lks.h
@@ -66,7 +93,8 @@ def test_abi_struct_layout_matches_header(tmp_path):
                    + "".join(f'printf(" %zu", offsetof(lks_config, {f}));\n' for f in fields)
                    + 'printf(" %zu %zu", offsetof(lks_buffers, sensors), offsetof(lks_buffers, scratch_bytes));'
                    + 'printf(" %zu %zu %zu", sizeof(lks_transport), offsetof(lks_transport, kappa), offsetof(lks_transport, per_rho));'
-                   + 'printf(" %d %d %d %d\\n", LKS_LAYOUT_PLANES, LKS_LAYOUT_ROWS, LKS_MODEL_BGK, LKS_MODEL_DDF);'
+                   + 'printf(" %d %d %d %d", LKS_LAYOUT_PLANES, LKS_LAYOUT_ROWS, LKS_MODEL_BGK, LKS_MODEL_DDF);'
+                   + 'printf(" %u\\n", (unsigned)LKS_NOALLOC_SCRATCH_BYTES);'
                    + "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
@@ -78,6 +106,7 @@ def test_abi_struct_layout_matches_header(tmp_path):
     want += [lks.Buffers.sensors.offset, lks.Buffers.scratch_bytes.offset]
     want += [ctypes.sizeof(lks.Transport), lks.Transport.kappa.offset, lks.Transport.per_rho.offset]
     want += [lks.LAYOUT_PLANES, lks.LAYOUT_ROWS, lks.MODEL_BGK, lks.MODEL_DDF]
+    want += [lks.NOALLOC_SCRATCH_BYTES]
     assert got == want
 
 

@@ -8,7 +8,7 @@ moments + equilibrium + S_KL, S_NEQ, S_PI + refinement flags + BGK collision +
 FP64 global sums, all in one kernel (plus one small reduction kernel per
 batch of steps).  Inputs are resident in HBM before the timed region starts.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--forms]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--cpu-full] [--forms]
                     [--ext] [--ddf] [--q25] [--regrid] [--no-two-step]
     python bench.py --mode kernel --steps 5      # short run for profilers
     python bench.py --mode copy                  # copy-kernel yardstick only
@@ -34,7 +34,8 @@ BYTES_F32_PLAIN = 193           # stream 36 + 36, sensors 36 + 13, collide 36 + 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2q9_fused_f32_4096.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_13618_amd", "csrc", "d2q9.hip")
 # the fused FP32 step at the default launch shape (4 cells per thread)
-FUSED_KERNEL = "d2q9_fused_lds<float,4,false>"
+# (non-temporal stores: the two 604 MB state buffers exceed the last-level cache)
+FUSED_KERNEL = "d2q9_fused_lds<float,4,false,true>"
 FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 # the double-distribution step (FP32): 50 x 4 read + 50 x 4 written + 5 x 4
 # sensors + 1 flag per cell (the method's bytes; the two kernels of the step
@@ -49,6 +50,17 @@ LAYOUT = "rows"                 # population layout of every lattice (--layout)
 
 
 RUNS = 5                        # timed runs per measurement; the median is reported
+
+
+def warm_up(torch, work, seconds=0.04):
+    """Sustained load before a timed leg: the chip's clocks dip a few
+    milliseconds into a burst of work and settle some 20 ms later (see
+    profiles/d2q9_fused_f32_4096_clock_ramp.md), so each leg runs its own
+    step for 40 ms first."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        work()
+        torch.cuda.synchronize()
 
 
 def median_time(torch, ev, runs, work, out=None):
@@ -77,14 +89,25 @@ def parse():
     p.add_argument("--warmup", type=int, default=60)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=40)
+    p.add_argument("--cpu-full", action="store_true",
+                   help="time the FP64 oracle alone on every workload (all cores and one thread, "
+                        "bounded samples of each) and print that JSON line; no GPU is used")
+    p.add_argument("--headline-only", action="store_true",
+                   help="skip the legs of the other forms (16-bit storage, D2Q25 single and "
+                        "double distribution, adjoint, two steps per launch)")
     p.add_argument("--forms", action="store_true",
-                   help="also time the BF16/FP16 storage forms on the 8192^2 workload")
+                   help="time the BF16/FP16 storage forms on the 8192^2 workload (the default)")
     p.add_argument("--ext", action="store_true",
                    help="also time the fused steps with every extension sensor on")
     p.add_argument("--ddf", action="store_true",
-                   help="also time the D2Q25 double-distribution step on the 2048^2 Riemann problem")
+                   help="time the D2Q25 double-distribution step on the 2048^2 Riemann problem "
+                        "(the default)")
     p.add_argument("--q25", action="store_true",
-                   help="also time the D2Q25 single-distribution step on the 2048^2 Riemann problem")
+                   help="time the D2Q25 single-distribution step on the 2048^2 Riemann problem "
+                        "(the default)")
+    p.add_argument("--adjoint", action="store_true",
+                   help="time the differentiation workload, forward and hand-written adjoint "
+                        "(the default)")
     p.add_argument("--two-step", action="store_true",
                    help="time two fused steps per launch (launch_steps = 2) against one, FP32 on "
                         "the 4096^2 and 8192^2 smooth fields (the default; kept for explicit use)")
@@ -194,6 +217,9 @@ def main():
     LAYOUT = args.layout
     if args.traffic_from:
         assemble_traffic(args.traffic_from)
+        return
+    if args.cpu_full:
+        print(json.dumps(cpu_full()), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -331,21 +357,25 @@ def main():
         "positivity_faults": faults,
     }
 
-    if args.forms:
+    # the other forms: reported beside the headline on the same GPU
+    legs = not args.headline_only
+    del lat
+    torch.cuda.empty_cache()
+    if legs or args.forms:
         out["forms"] = time_forms(torch, lks, inputs, workloads, dev, ev)
+    if legs or args.q25:
+        out["q25"] = time_q25(torch, lks, inputs, workloads, dev, ev)
+    if legs or args.ddf:
+        out["ddf"] = time_ddf(torch, lks, inputs, workloads, dev, ev)
+    if legs or args.adjoint:
+        out["adjoint"] = time_adjoint(torch, lks, inputs, workloads, dev, ev)
     if args.ext:
         out["ext"] = time_ext(torch, lks, inputs, workloads, dev, ev)
-    if args.ddf:
-        out["ddf"] = time_ddf(torch, lks, inputs, workloads, dev, ev)
-    if args.q25:
-        out["q25"] = time_q25(torch, lks, inputs, workloads, dev, ev)
-    if not args.no_two_step:
+    if legs and not args.no_two_step:
         out["two_step"] = time_two_step(torch, lks, inputs, workloads, dev, ev)
     if regrid is not None:
         out["regrid"] = regrid
 
-    del lat
-    torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, rho, ux, uy, wl)
     else:
@@ -442,14 +472,8 @@ def time_ext(torch, lks, inputs, workloads, dev, ev):
     for name, lat, nbytes in (("d2q9_4096_f32_ext9", a, 85 + 4 * len(EXT9)),
                               ("d2q25_2048_f32_ext8", b, 217 + 4 * len(EXT25)),
                               ("d2q25_ddf_2048_f32_ext8", c, BYTES_F32_DDF + 4 * len(EXT25))):
-        lat.step(3)
-        torch.cuda.synchronize()
-        s, e = ev(), ev()
-        s.record()
-        lat.step(k)
-        e.record()
-        torch.cuda.synchronize()
-        t = s.elapsed_time(e) / k * 1e-3
+        warm_up(torch, lambda: lat.step(1))
+        t = median_time(torch, ev, RUNS, lambda: lat.step(k)) / k
         cells = lat.nx * lat.ny
         res[name] = {"MLUPS": round(cells / t / 1e6, 1), "us_per_step": round(t * 1e6, 1),
                      "GBps_model": round(nbytes * cells / t / 1e9, 1), "bytes_per_lup": nbytes,
@@ -504,21 +528,14 @@ def time_q25(torch, lks, inputs, workloads, dev, ev):
 def time_d2q25(torch, ev, lat, k, name, kernel, bpl):
     """Whole steps, then the step kernel(s) alone between the two state buffers
     (after untimed steps that let the clocks settle)."""
-    lat.step(20)
-    torch.cuda.synchronize()
-    s, e = ev(), ev()
-    s.record()
-    lat.step(k)
-    e.record()
-    torch.cuda.synchronize()
-    t = s.elapsed_time(e) / k * 1e-3
+    warm_up(torch, lambda: lat.step(1))
+    t = median_time(torch, ev, RUNS, lambda: lat.step(k)) / k
     src, dst = lat.pop[lat.current()[0]], lat.pop[1 - lat.current()[0]]
-    s.record()
-    for r in range(k):
-        lat.step_from(src, dst) if r % 2 == 0 else lat.step_from(dst, src)
-    e.record()
-    torch.cuda.synchronize()
-    tk = s.elapsed_time(e) / k * 1e-3
+
+    def alone():
+        for r in range(k):
+            lat.step_from(src, dst) if r % 2 == 0 else lat.step_from(dst, src)
+    tk = median_time(torch, ev, RUNS, alone) / k
     cells = lat.nx * lat.ny
     res = {"workload": name, "MLUPS": round(cells / t / 1e6, 1),
            "us_per_step": round(t * 1e6, 1), "kernel": kernel, "kernel_us": round(tk * 1e6, 1),
@@ -616,6 +633,30 @@ def time_two_step(torch, lks, inputs, workloads, dev, ev, k=32, rounds=RUNS):
     return res
 
 
+def time_adjoint(torch, lks, inputs, workloads, dev, ev):
+    """The differentiation workload (D2Q9 1024^2 FP32, 200 steps, checkpoint
+    every 20): the forward run keeping checkpoints plus the backward pass
+    (segment recompute and the hand-written adjoint kernels) behind
+    torch.autograd, median of RUNS after one untimed pass."""
+    from paper_2603_13618_amd import adjoint
+    wl = workloads.ADJOINT_1024
+    n, steps, K = wl["nx"], wl["steps"], wl["checkpoint"]
+    rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+    r = torch.tensor(rho, device=dev)
+    u0, v0 = torch.tensor(ux, device=dev), torch.tensor(uy, device=dev)
+
+    def run():
+        u, v = u0.clone().requires_grad_(True), v0.clone().requires_grad_(True)
+        L = adjoint.kl_sensor_loss(u, v, r, tau=wl["tau"], nsteps=steps, checkpoint=K, dtype="f32",
+                                   layout=LAYOUT)
+        L.backward()
+    warm_up(torch, run)
+    t = median_time(torch, ev, RUNS, run)
+    return {"workload": wl["name"], "ms_forward_backward": round(t * 1e3, 3),
+            "steps": steps, "checkpoint": K,
+            "MLUPS_forward_equivalent": round(n * n * steps / t / 1e6, 1)}
+
+
 def time_forms(torch, lks, inputs, workloads, dev, ev):
     """BF16 / FP16 deviation storage on the 8192^2 smooth field (timing only)."""
     wl = workloads.SMOOTH_8192
@@ -626,15 +667,9 @@ def time_forms(torch, lks, inputs, workloads, dev, ev):
         lat = lks.Lattice(9, n, n, dtype, tau=wl["tau"], thr=wl["thr"] or workloads.SMOOTH_4096["thr"],
                           flag_mask=wl["flag_mask"], max_steps=64, layout=LAYOUT, device=dev)
         lat.init(rho, ux, uy)
-        lat.step(5)
-        torch.cuda.synchronize()
-        s, e = ev(), ev()
+        warm_up(torch, lambda: lat.step(1))
         k = 40
-        s.record()
-        lat.step(k)
-        e.record()
-        torch.cuda.synchronize()
-        t = s.elapsed_time(e) / k * 1e-3
+        t = median_time(torch, ev, RUNS, lambda: lat.step(k)) / k
         res[dtype] = {"MLUPS": round(n * n / t / 1e6, 1), "GBps_model": round(nbytes * n * n / t / 1e9, 1),
                       "bytes_per_lup": nbytes, "grid": [n, n]}
         del lat
@@ -695,6 +730,52 @@ def cpu_baseline(steps, rho, ux, uy, wl, steps_1thread=2):
             "sample_1thread": f"the same grid, {steps_1thread} steps on one thread, {t1:.1f} s",
             "double_shear_128": {"MLUPS": round(128 * 128 * 500 / tc1 / 1e6, 2), "cores": threads,
                                  "sample": f"128x128 D2Q9 FP64, tau 0.55, all 500 steps, {tc1:.2f} s"}}
+
+
+def cpu_full():
+    """The FP64 oracle on each workload, on every core this process may use
+    and on one thread: the whole double shear layer (128^2, 500 steps) and
+    bounded samples of the others (the full grid for a few steps)."""
+    import oracle
+    from paper_2603_13618_amd import inputs, workloads
+    threads = host_threads()
+    res = {"cpu_model": cpu_model(), "cores": threads, "kind": "oracle", "unit": "MLUPS"}
+
+    def rate(name, cells, runs):
+        out = {}
+        for label, nthr, steps, fn in runs:
+            fn(1, nthr)                                  # page-in
+            t0 = time.perf_counter()
+            fn(steps, nthr)
+            t = time.perf_counter() - t0
+            out[label] = {"MLUPS": round(cells * steps / t / 1e6, 3), "steps": steps, "s": round(t, 2)}
+        res[name] = out
+
+    r, u, v = inputs.double_shear_layer(128)
+    f1 = oracle.equilibrium(9, r, u, v)
+    rate("double_shear_128_d2q9", 128 * 128,
+         [(f"{threads}_threads", threads, 500, lambda k, t: oracle.run(9, f1, k, tau=0.55, nthreads=t)),
+          ("1_thread", 1, 500, lambda k, t: oracle.run(9, f1, k, tau=0.55, nthreads=t))])
+    for wl, k_all, k_one in ((workloads.SMOOTH_4096, 20, 2), (workloads.SMOOTH_8192, 5, 1)):
+        n = wl["nx"]
+        r, u, v = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+        f = oracle.equilibrium(9, r, u, v)
+        del r, u, v
+        rate(f"smooth_{n}_d2q9", n * n,
+             [(f"{threads}_threads", threads, k_all, lambda k, t: oracle.run(9, f, k, tau=wl["tau"], nthreads=t)),
+              ("1_thread", 1, k_one, lambda k, t: oracle.run(9, f, k, tau=wl["tau"], nthreads=t))])
+        del f
+    wq = workloads.RIEMANN_2048
+    n = wq["nx"]
+    r, u, v, T, states = inputs.riemann_quadrants(n, seed=wq["seed"])
+    dx = 1.0 / n
+    dt = inputs.riemann_dt(states, dx)
+    f = oracle.equilibrium(25, r, u, v, T)
+    rate(f"riemann_{n}_d2q25", n * n,
+         [(f"{threads}_threads", threads, 4,
+           lambda k, t: oracle.run(25, f, k, mu=wq["mu"], dt=dt, dx=dx, bc=(1, 1), nthreads=t)),
+          ("1_thread", 1, 1, lambda k, t: oracle.run(25, f, k, mu=wq["mu"], dt=dt, dx=dx, bc=(1, 1), nthreads=t))])
+    return res
 
 
 if __name__ == "__main__":

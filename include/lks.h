@@ -178,8 +178,10 @@ typedef struct {
                              in the compute precision; +INF disables           */
     int32_t max_steps;    /* rows of the sums buffer, >= 1                     */
     int32_t launch_vec;   /* cells per thread along x of the cell kernels (1, 2
-                             or 4); 0 picks the widest the row length and the
-                             buffer alignment allow (a launch-shape hint only) */
+                             or 4); 0 picks 4 for F32 and 2 for the other
+                             storage types, or fewer where the row length or
+                             the buffer alignment do not allow it (a
+                             launch-shape hint only)                           */
     uint32_t ext_mask;    /* extension sensors to compute and store, LKS_X_*
                              bits (0 = none)                                   */
     int32_t ext_reserved; /* must be 0                                          */
@@ -202,9 +204,12 @@ typedef struct {
                              an odd last step of a reduction batch runs
                              alone; a batch holds at most max_steps steps,
                              so max_steps = 1 runs one step per launch).
-                             A launch hint: the results are the same bits,
-                             but the state changes buffer once per launch,
-                             so lks_current names the buffer that holds it */
+                             A launch hint: state, sensors, flags and the
+                             fault count are the same bits and the per-step
+                             FP64 sums agree to FP64 rounding (each cell's
+                             terms are widened to FP64 before any add), but
+                             the state changes buffer once per launch, so
+                             lks_current names the buffer that holds it      */
 } lks_config;
 
 typedef struct {

@@ -63,12 +63,17 @@
 #define LKS_DDF_WAVES 2
 #endif
 // FP32 tile of the double distribution's g kernel (its own launch grid): as
-// for the single distribution, rows of 32 cells stage whole 128-byte lines
+// for the single distribution, rows of 32 cells stage whole 128-byte lines;
+// and the waves per SIMD its register allocation must allow (it fits five
+// without spilling)
 #ifndef LKS_DDF_G_TX
 #define LKS_DDF_G_TX 32
 #endif
 #ifndef LKS_DDF_G_TY
 #define LKS_DDF_G_TY 8
+#endif
+#ifndef LKS_DDF_G_WAVES
+#define LKS_DDF_G_WAVES 5
 #endif
 
 namespace lks {
@@ -204,13 +209,18 @@ __device__ __forceinline__ R flux_diff(R qm2, R qm1, R q0, R qp1, R qp2)
 
 // Workgroup -> tile.  Consecutive workgroup ids go to the eight XCDs in turn
 // (id mod 8), each with its own L2, so the order decides which halo rows and
-// columns a tile finds in its XCD's L2.  LKS_Q25_XCD_MAP 0: XCD k sweeps
-// column band k of the tile columns row by row; 1: XCD k sweeps row band k
-// of the tile rows row by row (whole grid rows: only the band's first and
-// last tile rows read a halo another XCD loaded); 2: plain row-major order.
-// Shapes that do not divide into 8 bands use row-major order.
+// columns a tile finds in its XCD's L2.  LKS_Q25_XCD_MAP 1 (default): XCD k
+// sweeps row band k of the tile rows row by row, so the halo columns always
+// come from its own L2 and only the band's first and last tile rows read
+// halo rows another XCD loaded; 0: XCD k sweeps column band k of the tile
+// columns row by row (every band edge reads its halo columns from another
+// XCD's band); 2: plain row-major order.  Measured at 2048^2 (FP32 kernel
+// time per step, a 3-wave build of the single-distribution kernel): single
+// distribution 354 / 376 / 362 us for maps 1 / 0 / 2, double distribution
+// 799 / 808 / 877 us.  Shapes that do not divide into 8 bands use row-major
+// order.
 #ifndef LKS_Q25_XCD_MAP
-#define LKS_Q25_XCD_MAP 0
+#define LKS_Q25_XCD_MAP 1
 #endif
 __device__ __forceinline__ void xcd_tile(const D2Q25Args& a, int& tile_x, int& tile_y)
 {
@@ -344,7 +354,7 @@ template <> struct Q25Waves<float> { static constexpr int v = LKS_Q25_WAVES > 0 
 // Unlike TileStage, only the threads with a halo cell load one: here that
 // keeps the kernel at 121 registers (four waves per SIMD) and measured 7 %
 // faster than the unconditional form.
-template <typename S, int TX, int TY, bool EXT = false>
+template <typename S, int TX, int TY, bool EXT = false, bool EDGE = true>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Waves<S>::v))) void d2q25_kernel(D2Q25Args a, const typename Store<S>::raw* __restrict__ fin,
                                                    typename Store<S>::raw* __restrict__ fout,
                                                    typename Store<S>::real* __restrict__ sens,
@@ -365,7 +375,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int X0 = tile_x * TX, Y0 = tile_y * TY;
     const int X = X0 + tx, Y = Y0 + ty;
-    const bool active = X < nx && Y < ny;
+    // EDGE = false: the grid is a whole number of tiles, every thread owns a
+    // cell, and no store needs a branch around it (a branch per store cuts
+    // the arithmetic of a velocity group into separate scheduling regions)
+    const bool active = !EDGE || (X < nx && Y < ny);
     const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
     constexpr int HR = (4 * TX + NT - 1) / NT;
     const long long own = (long long)gyc * a.L.pr + gxc;
@@ -434,12 +447,12 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
         edev += R(0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))) * v;
     });
     const R rho = rho0 + drho;
-    const R irho = R(1) / rho;
+    const R irho = rcp(rho);
     const R ux = jx * irho, uy = jy * irho;
     // T = (2E/rho - |u|^2)/2 with E = rho0 + edev (sum_i w_i |v_i|^2/2 = 1)
     const R tm1 = (edev - drho) * irho - R(0.5) * (ux * ux + uy * uy);
     const R A = R(a.dt / a.dx);
-    const R B = R(a.dt) * rho * (R(1) + tm1) / R(a.mu);   // dt / tau
+    const R B = R(a.dt / a.mu) * rho * (R(1) + tm1);   // dt / tau
     const Deq25<R> eq(drho, rho, ux, uy, tm1);
 
     write_group(std::integral_constant<int, 0>{});
@@ -447,9 +460,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
 
     const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
                        T::rowbase(ty + 2)};
-    // sxx = sum (xi_a^2 - xi_b^2)/2 d, sxy = sum xi_a xi_b d: raw stress
-    // moments behind S_PI (below)
-    R kl = R(0), neq = R(0), qx = R(0), qy = R(0), sxx = R(0), sxy = R(0);
+    // pxx, pxy: the non-equilibrium stress behind S_PI (below)
+    R kl = R(0), neq = R(0), qx = R(0), qy = R(0), pxx = R(0), pxy = R(0);
     R xmin = R(0), xmax = R(0), feqmin = R(0);
     bool first = true;
     const long long off = (long long)Y * nx + X;
@@ -466,12 +478,15 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
             const R fneq = d - deq;
             const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
             const R x = fneq * rcp(feq);
-            kl += (fneq * x) * kl_series(x);           // series branch; fallback below
-            xmin = first ? x : fmin(xmin, x);
+            kl += (fneq * x) * kl_series_short(x);     // series branch; fallback below
             xmax = first ? fabs(x) : fmax(xmax, fabs(x));
             feqmin = first ? feq : fmin(feqmin, feq);
             first = false;
             neq += fabs(fneq);
+            // explicit multiply-adds (contraction fixed in every instantiation)
+            if (ia != ib && ia != 4 - ib)
+                pxx = fma(R(0.5 * (gh5_xi(ia) * gh5_xi(ia) - gh5_xi(ib) * gh5_xi(ib))), fneq, pxx);
+            if (ia != 2 && ib != 2) pxy = fma(R(gh5_xi(ia) * gh5_xi(ib)), fneq, pxy);
             const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
             const R e = R(0.5) * (vx * vx + vy * vy);
             qx += vx * e * fneq;
@@ -494,51 +509,44 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
             __syncthreads();
         }
     });
-    if (!(xmax <= KlCut<R>::v)) {
-        // rare: some population far from equilibrium (or NaN): the closed form
+    // rare: some population far from equilibrium (or NaN): the longer series
+    // or the closed form, population by population, and the smallest x
+    // (x > -1 is f > 0; on the short-series branch |x| <= 0.03 implies it)
+    const bool far = !(xmax <= KlShortCut<R>::v);
+    if (far) {
         kl = R(0);
+        first = true;
         d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
             const R d = vin[5 * ia + ib];
             const R feq = R(gh5_w(ia) * gh5_w(ib)) * rho0 + deq;
-            kl += feq * kl_phi((d - deq) * rcp(feq));
+            const R x = (d - deq) * rcp(feq);
+            xmin = first ? x : fmin(xmin, x);
+            first = false;
+            kl += feq * kl_phi(x);
         });
     }
 
-    // Non-equilibrium stress P = sum v v f^neq.  The order-4 equilibrium
-    // carries the Maxwellian's second moment exactly (GH5 integrates degree
-    // 9), sum v v f^eq = rho (u u + T I), and T comes from this cell's own
-    // energy, so tr P = 0: P = [[pxx, pxy], [pxy, -pxx]] with pxx = sxx -
-    // rho (ux^2 - uy^2)/2, pxy = sxy - rho ux uy (sum v v w rho0 = rho0 I
-    // cancels in both).  From the raw moments it carries no rounding of the
-    // 25 equilibrium populations: about 6x less FP32 error than summing
-    // v v (d - d^eq), and 24 fewer multiply-adds.
-    sfor25<25>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        constexpr int ia = i / 5, ib = i % 5;
-        if constexpr (ia != ib && ia != 4 - ib)
-            sxx += R(0.5 * (gh5_xi(ia) * gh5_xi(ia) - gh5_xi(ib) * gh5_xi(ib))) * vin[i];
-        if constexpr (ia != 2 && ib != 2) sxy += R(gh5_xi(ia) * gh5_xi(ib)) * vin[i];
-    });
-    const R pxx = sxx - R(0.5) * rho * ((ux - uy) * (ux + uy));
-    const R pxy = sxy - rho * ux * uy;
+    // Non-equilibrium stress P = sum v v f^neq.  T comes from this cell's own
+    // energy and the order-4 equilibrium carries the Maxwellian's energy
+    // exactly (GH5 integrates degree 9), so tr P = 2 (E - E^eq) = 0 and P =
+    // [[pxx, pxy], [pxy, -pxx]] with pxx = sum (xi_a^2 - xi_b^2)/2 f^neq: the
+    // trace, where the rounding of the 25 equilibrium populations
+    // concentrates, never enters (FP32 error about 6x smaller than the three
+    // components summed separately, and 20 fewer multiply-adds).
     const R pyy = -pxx;
-    const bool fault = !(feqmin > R(0)) || !(xmin > R(-1)) || !(kl == kl);
+    const bool fault = !(feqmin > R(0)) || (far && !(xmin > R(-1))) || !(kl == kl);
     const R s_kl = fault ? R(INFINITY) : kl;
-    const R s_pi = sqrt(R(2) * (pxx * pxx + pxy * pxy));
-    const R s_q = sqrt(qx * qx + qy * qy);
+    // explicit multiply-adds: the same bits in every instantiation
+    const R s_pi = sqrt_r(R(2) * fma(pxx, pxx, pxy * pxy));
+    const R s_q = sqrt_r(fma(qx, qx, qy * qy));
     double acc[kNsums];
 #pragma unroll
     for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
     if (active) {
         const R sv[4] = {s_kl, neq, s_pi, s_q};
-        int level = 0;
+        LevelAcc lv;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (a.mask & (1u << s)) {
-                const int l = (sv[s] > R(a.thr[s][0])) + (sv[s] > R(a.thr[s][1]));
-                level = l > level ? l : level;
-            }
-        }
+        for (int s = 0; s < 4; ++s) lv.add(sv[s], R(a.thr[s][0]), R(a.thr[s][1]));
         if constexpr (EXT) {
             // A separate pass on opaque copies (pin) of the moments and of the
             // cell's populations, after the base arithmetic: no base
@@ -565,17 +573,14 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
 #pragma unroll
             for (int q = 0; q < kNumExt; ++q) {
                 if (a.x.plane[q] >= 0) sens[a.x.plane[q] * plane + off] = xv[q];
-                if (a.mask & (1u << (kExtFlagShift + q))) {
-                    const int l = (xv[q] > R(a.x.thr[q][0])) + (xv[q] > R(a.x.thr[q][1]));
-                    level = l > level ? l : level;
-                }
+                if (a.mask & (1u << (kExtFlagShift + q))) lv.add(xv[q], R(a.x.thr[q][0]), R(a.x.thr[q][1]));
             }
         }
         sens[off] = s_kl;
         sens[plane + off] = neq;
         sens[2 * plane + off] = s_pi;
         sens[3 * plane + off] = s_q;
-        flags[off] = fault ? uint8_t(0x82) : uint8_t(level);
+        flags[off] = fault ? uint8_t(0x82) : uint8_t(lv.level());
         if (fault) atomicAdd(faults, 1ull);
         acc[0] = (double)drho;
         acc[1] = (double)jx;
@@ -619,8 +624,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
 // registers each: there the hint would spill hundreds)
 template <typename S> struct DdfWaves { static constexpr int v = 1; };
 template <> struct DdfWaves<float> { static constexpr int v = LKS_DDF_WAVES > 0 ? LKS_DDF_WAVES : 1; };
+template <typename S> struct DdfGWaves { static constexpr int v = 1; };
+template <> struct DdfGWaves<float> { static constexpr int v = LKS_DDF_G_WAVES > 0 ? LKS_DDF_G_WAVES : 1; };
 
-template <typename S, int TX, int TY, bool EXT = false>
+template <typename S, int TX, int TY, bool EXT = false, bool EDGE = true>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWaves<S>::v))) void d2q25_ddf_kernel(
     D2Q25Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ partials,
@@ -638,7 +645,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int X0 = tile_x * TX, Y0 = tile_y * TY;
     const int X = X0 + tx, Y = Y0 + ty;
-    const bool active = X < nx && Y < ny;
+    const bool active = !EDGE || (X < nx && Y < ny);     // EDGE: as in d2q25_kernel
     const int gxc = ghost_index(X, nx, a.bc_x), gyc = ghost_index(Y, ny, a.bc_y);
 
     constexpr int HR = (4 * TX + NT - 1) / NT;
@@ -711,11 +718,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         dg0 += gc[i];
     });
     const R rho = rho0 + drho;
-    const R irho = R(1) / rho;
+    const R irho = rcp(rho);
     const R ux = jx * irho, uy = jy * irho;
     // C_v (T - 1) = (E - C_v rho)/rho - |u|^2/2 with E - C_v rho = dg0 + m2/2
     // - C_v drho (sum_i w_i = 1, sum_i w_i |v_i|^2/2 = 1: the reference parts cancel)
-    const R tm1 = ((dg0 + R(0.5) * m2 - cv * drho) * irho - R(0.5) * (ux * ux + uy * uy)) / cv;
+    const R tm1 = ((dg0 + R(0.5) * m2 - cv * drho) * irho - R(0.5) * (ux * ux + uy * uy)) * R(1.0 / a.cv);
     const R Tc = R(1) + tm1;
     const R gfac = cv - R(1);                              // g^eq = (C_v - 1) T f^eq
 
@@ -739,15 +746,17 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const R gneq = gc[i] - dgeq;
         const R geq = gfac * (w * rho0) + dgeq;
         const R y = gneq * rcp(geq);
-        klf += (fneq * x) * kl_series(x);
-        klg += (gneq * y) * kl_series(y);
+        klf += (fneq * x) * kl_series_short(x);
+        klg += (gneq * y) * kl_series_short(y);
         gsum += gneq;
         nonpos = nonpos || !(feq > R(0)) || !(geq > R(0)) || !(x > R(-1)) || !(y > R(-1));
-        far = far || !(fabs(x) <= KlCut<R>::v) || !(fabs(y) <= KlCut<R>::v);
+        far = far || !(fabs(x) <= KlShortCut<R>::v) || !(fabs(y) <= KlShortCut<R>::v);
         neq += fabs(fneq) + fabs(gneq);
-        pxx += vx * vx * fneq;
-        pxy += vx * vy * fneq;
-        pyy += vy * vy * fneq;
+        // explicit multiply-adds: the contraction of the stress sums is fixed,
+        // so S_PI is the same bits with and without the extension sensors
+        pxx = fma(vx * vx, fneq, pxx);
+        pxy = fma(vx * vy, fneq, pxy);
+        pyy = fma(vy * vy, fneq, pyy);
         const R e = R(0.5) * (vx * vx + vy * vy);
         qx += vx * (gneq + e * fneq);
         qy += vy * (gneq + e * fneq);
@@ -865,7 +874,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     // ---- pass 2: f' = f - A div - (dt/tau1)(f - f^eq) + (dt/tau1 - dt/tau2)(f* - f^eq),
     //      f first, then g through the same buffer
     const R A = R(a.dt / a.dx);
-    const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
+    const R B1 = R(a.dt / a.mu) * rho * Tc;                // dt / tau1
     const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
     const long long off = (long long)Y * nx + X;
     const long long poff = a.L.at(0, Y, X);
@@ -920,36 +929,31 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     const R klsum = fabs(klf) + fabs(klg + gsum);
     const bool fault = nonpos || !(klsum == klsum);
     const R s_kl = fault ? R(INFINITY) : klsum;
-    const R s_pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
-    const R s_q = sqrt(qxo * qxo + qyo * qyo);
+    // explicit multiply-adds: the same bits with and without the extension
+    const R s_pi = sqrt_r(fma(pxx, pxx, fma(R(2) * pxy, pxy, pyy * pyy)));
+    const R s_q = sqrt_r(fma(qxo, qxo, qyo * qyo));
     double acc[kNsums];
 #pragma unroll
     for (int k = 0; k < kNsums; ++k) acc[k] = 0.0;
     if (active) {
         const R sv[5] = {s_kl, neq, s_pi, s_q, qe};
-        int level = 0;
+        LevelAcc lv;
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            if (a.mask & (1u << s)) {
-                const R t0 = s < 4 ? R(a.thr[s][0]) : R(a.thr_qe[0]);
-                const R t1 = s < 4 ? R(a.thr[s][1]) : R(a.thr_qe[1]);
-                const int l = (sv[s] > t0) + (sv[s] > t1);
-                level = l > level ? l : level;
-            }
+            const R t0 = s < 4 ? R(a.thr[s][0]) : R(a.thr_qe[0]);
+            const R t1 = s < 4 ? R(a.thr[s][1]) : R(a.thr_qe[1]);
+            lv.add(sv[s], t0, t1);
         }
         if constexpr (EXT) {
             sfor25<kNumExt>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 if (a.x.plane[q] >= 0) sens[a.x.plane[q] * plane + off] = xv[q];
-                if (a.mask & (1u << (kExtFlagShift + q))) {
-                    const int l = (xv[q] > R(a.x.thr[q][0])) + (xv[q] > R(a.x.thr[q][1]));
-                    level = l > level ? l : level;
-                }
+                if (a.mask & (1u << (kExtFlagShift + q))) lv.add(xv[q], R(a.x.thr[q][0]), R(a.x.thr[q][1]));
             });
         }
 #pragma unroll
         for (int s = 0; s < 5; ++s) sens[s * plane + off] = sv[s];
-        flags[off] = fault ? uint8_t(0x82) : uint8_t(level);
+        flags[off] = fault ? uint8_t(0x82) : uint8_t(lv.level());
         if (fault) atomicAdd(faults, 1ull);
         acc[0] = (double)drho;
         acc[1] = (double)jx;
@@ -969,8 +973,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
 // g' = g - A div - (dt/tau1)(g - g^eq) + (dt/tau1 - dt/tau2)(g* - g^eq).
 // Splitting the step here keeps the f kernel within two waves per SIMD
 // without spilling registers.
-template <typename S, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
+template <typename S, int TX, int TY, bool EDGE = true>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfGWaves<S>::v))) void d2q25_ddf_g_kernel(D2Q25Args a,
                                                          const typename Store<S>::raw* __restrict__ fin,
                                                          typename Store<S>::raw* __restrict__ fout)
 {
@@ -987,7 +991,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int X0 = tile_x * TX, Y0 = tile_y * TY;
     const int X = X0 + tx, Y = Y0 + ty;
-    const bool active = X < nx && Y < ny;
+    const bool active = !EDGE || (X < nx && Y < ny);     // EDGE: as in d2q25_kernel
     const TileStage<S, TX, TY> st(a, X0, Y0, tx, ty);
     constexpr int HR = TileStage<S, TX, TY>::HR;
     const int rb[5] = {T::rowbase(ty - 2), T::rowbase(ty - 1), T::rowbase(ty), T::rowbase(ty + 1),
@@ -1023,7 +1027,7 @@ __global__ __launch_bounds__(TX * TY) void d2q25_ddf_g_kernel(D2Q25Args a,
     const R rho = rho0 + drho;
     const R Tc = R(1) + tm1;
     const R A = R(a.dt / a.dx);
-    const R B1 = R(a.dt) * rho * Tc / R(a.mu);             // dt / tau1
+    const R B1 = R(a.dt / a.mu) * rho * Tc;                // dt / tau1
     const R B12 = B1 * (R(1) - R(a.prandtl));              // dt / tau1 - dt / tau2
     const Deq25<R> eq(drho, rho, ux, uy, tm1);
 
@@ -1077,11 +1081,19 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
     if (!a.aux) return hipErrorInvalidValue;
-    if (a.x.mask)
-        d2q25_ddf_kernel<S, TX, TY, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+    // the same EDGE form with and without the extension sensors (as above)
+    const bool whole = a.nx % TX == 0 && a.ny % TY == 0;
+    if (a.x.mask && whole)
+        d2q25_ddf_kernel<S, TX, TY, true, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (a.x.mask)
+        d2q25_ddf_kernel<S, TX, TY, true, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (whole)
+        d2q25_ddf_kernel<S, TX, TY, false, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     else
-        d2q25_ddf_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+        d2q25_ddf_kernel<S, TX, TY, false, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     D2Q25Args ag = a;
@@ -1090,7 +1102,10 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
     ag.tiles_x = (a.nx + GX - 1) / GX;
     ag.tiles_y = (a.ny + GY - 1) / GY;
     ag.nblocks = ag.tiles_x * ag.tiles_y;
-    d2q25_ddf_g_kernel<S, GX, GY><<<dim3(ag.nblocks), dim3(GX * GY), 0, s>>>(ag, (const raw*)fin, (raw*)fout);
+    if (a.nx % GX == 0 && a.ny % GY == 0)
+        d2q25_ddf_g_kernel<S, GX, GY, false><<<dim3(ag.nblocks), dim3(GX * GY), 0, s>>>(ag, (const raw*)fin, (raw*)fout);
+    else
+        d2q25_ddf_g_kernel<S, GX, GY><<<dim3(ag.nblocks), dim3(GX * GY), 0, s>>>(ag, (const raw*)fin, (raw*)fout);
     return hipGetLastError();
 }
 
@@ -1101,11 +1116,20 @@ static hipError_t launch_tile(const D2Q25Args& a, const void* fin, void* fout, v
     using raw = typename Store<S>::raw;
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
-    if (a.x.mask)
-        d2q25_kernel<S, TX, TY, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+    // with and without the extension sensors the same EDGE form runs, so the
+    // base outputs stay the same bits
+    const bool whole = a.nx % TX == 0 && a.ny % TY == 0;
+    if (a.x.mask && whole)
+        d2q25_kernel<S, TX, TY, true, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (a.x.mask)
+        d2q25_kernel<S, TX, TY, true, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (whole)
+        d2q25_kernel<S, TX, TY, false, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     else
-        d2q25_kernel<S, TX, TY><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+        d2q25_kernel<S, TX, TY, false, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     return hipGetLastError();
 }

@@ -127,6 +127,7 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
     if constexpr (SENSE) {
         R kl = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0);
         R xmax = R(0), xmin = R(0), feqmin = R(0);
+        bool far;
         {   // multiply-adds fuse within one expression only: the same bits in every kernel
 #pragma clang fp contract(on)
 #pragma unroll
@@ -135,28 +136,33 @@ __device__ __forceinline__ CellSense<R> cell_update(R (&d)[9], R rho0, R inv_tau
                 const R feq = w9<R>(i) * rho0 + deq[i];
                 const R x = fneq * rcp(feq);
                 // S_KL term feq phi(x) = fneq x p(x) on the series branch
-                kl += (fneq * x) * kl_series(x);
+                kl += (fneq * x) * kl_series_short(x);
                 xmax = i == 0 ? fabs(x) : fmax(xmax, fabs(x));
-                xmin = i == 0 ? x : fmin(xmin, x);
                 feqmin = i == 0 ? feq : fmin(feqmin, feq);
                 neq += fabs(fneq);
                 if (cx9(i) != 0) pxx += fneq;
                 if (cy9(i) != 0) pyy += fneq;
                 if (cx9(i) * cy9(i) != 0) pxy += R(cx9(i) * cy9(i)) * fneq;
             }
-            if (!(xmax <= KlCut<R>::v)) {       // rare: far from equilibrium (or NaN)
+            // Rare: some population far from equilibrium (or NaN).  There the
+            // smallest x is needed too (x > -1 is f > 0); on the short-series
+            // branch |x| <= 0.03 already implies it.
+            far = !(xmax <= KlShortCut<R>::v);
+            if (far) {
                 kl = R(0);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     const R feq = w9<R>(i) * rho0 + deq[i];
-                    kl += feq * kl_phi((d[i] - deq[i]) * rcp(feq));
+                    const R x = (d[i] - deq[i]) * rcp(feq);
+                    xmin = i == 0 ? x : fmin(xmin, x);
+                    kl += feq * kl_phi(x);
                 }
             }
         }
-        out.fault = !(feqmin > R(0)) || !(xmin > R(-1)) || !(kl == kl);
+        out.fault = !(feqmin > R(0)) || (far && !(xmin > R(-1))) || !(kl == kl);
         out.kl = out.fault ? R(INFINITY) : kl;
         out.neq = neq;
-        out.pi = sqrt(pxx * pxx + R(2) * pxy * pxy + pyy * pyy);
+        out.pi = sqrt_r(fma(pxx, pxx, fma(R(2) * pxy, pxy, pyy * pyy)));
         if constexpr (EXT) {
             // The extension sensors work on opaque copies (pin) of the
             // pre-collision deviations, their equilibrium parts and the
@@ -287,7 +293,6 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
         } else {
             R s_kl[VEC], s_neq[VEC], s_pi[VEC];
             uint8_t fl[VEC];
-            R rsum[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
             for (int k = 0; k < VEC; ++k) {
                 R dc[9];
@@ -299,37 +304,27 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_kernel(
 #pragma unroll
                 for (int i = 0; i < 9; ++i) cur[i][k] = dc[i];
                 if constexpr (SENSE) {
-                    int level = 0;
+                    LevelAcc lv;
                     const R sv[3] = {cs.kl, cs.neq, cs.pi};
 #pragma unroll
-                    for (int s = 0; s < 3; ++s) {
-                        if (a.mask & (1u << s)) {
-                            const int l = (sv[s] > th[s][0]) + (sv[s] > th[s][1]);
-                            level = l > level ? l : level;
-                        }
-                    }
-                    fl[k] = cs.fault ? uint8_t(0x82) : uint8_t(level);
+                    for (int s = 0; s < 3; ++s) lv.add(sv[s], th[s][0], th[s][1]);
+                    fl[k] = cs.fault ? uint8_t(0x82) : uint8_t(lv.level());
                     s_kl[k] = cs.kl;
                     s_neq[k] = cs.neq;
                     s_pi[k] = cs.pi;
                     if (active) {
-                        rsum[0] += drho;
-                        rsum[1] += jx;
-                        rsum[2] += jy;
-                        rsum[3] += cs.kl;
-                        rsum[4] += cs.neq;
-                        rsum[5] += cs.pi;
+                        // each cell's terms widen to FP64 before any add: FP64
+                        // sums of FP32 values do not depend on the grouping,
+                        // i.e. on the launch shape
+                        acc[0] += (double)drho;
+                        acc[1] += (double)jx;
+                        acc[2] += (double)jy;
+                        acc[4] += (double)cs.kl;
+                        acc[5] += (double)cs.neq;
+                        acc[6] += (double)cs.pi;
                         nfault += cs.fault ? 1u : 0u;
                     }
                 }
-            }
-            if constexpr (SENSE) {
-                acc[0] += (double)rsum[0];
-                acc[1] += (double)rsum[1];
-                acc[2] += (double)rsum[2];
-                acc[4] += (double)rsum[3];
-                acc[5] += (double)rsum[4];
-                acc[6] += (double)rsum[5];
             }
             if (active) {
                 if constexpr (COLLIDE) {
@@ -534,7 +529,6 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
         // row's whole computation to cover both (stores count in vmcnt too)
         if (y > y0) store_row(y - 1);
 
-        R rsum[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
             R dc[9];
@@ -547,15 +541,10 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
                                                                     a.x.mask);
 #pragma unroll
             for (int i = 0; i < 9; ++i) res[i][k] = dc[i];
-            int level = 0;
+            LevelAcc lv;
             const R sv[3] = {cs.kl, cs.neq, cs.pi};
 #pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                if (a.mask & (1u << s)) {
-                    const int l = (sv[s] > th[s][0]) + (sv[s] > th[s][1]);
-                    level = l > level ? l : level;
-                }
-            }
+            for (int s = 0; s < 3; ++s) lv.add(sv[s], th[s][0], th[s][1]);
             if constexpr (EXT) {
 #pragma unroll
                 for (int q = 0; q < kNumExt; ++q) {
@@ -563,31 +552,25 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
                     if (a.mask & (1u << (kExtFlagShift + q))) {
                         const R t0 = F32 ? R(a.x.thr_f[q][0]) : R(a.x.thr[q][0]);
                         const R t1 = F32 ? R(a.x.thr_f[q][1]) : R(a.x.thr[q][1]);
-                        const int l = (xv[q] > t0) + (xv[q] > t1);
-                        level = l > level ? l : level;
+                        lv.add(xv[q], t0, t1);
                     }
                 }
             }
-            fl[k] = cs.fault ? uint8_t(0x82) : uint8_t(level);
+            fl[k] = cs.fault ? uint8_t(0x82) : uint8_t(lv.level());
             s_kl[k] = cs.kl;
             s_neq[k] = cs.neq;
             s_pi[k] = cs.pi;
             if (active) {
-                rsum[0] += drho;
-                rsum[1] += jx;
-                rsum[2] += jy;
-                rsum[3] += cs.kl;
-                rsum[4] += cs.neq;
-                rsum[5] += cs.pi;
+                // each cell's terms widen to FP64 before any add (as above)
+                acc[0] += (double)drho;
+                acc[1] += (double)jx;
+                acc[2] += (double)jy;
+                acc[4] += (double)cs.kl;
+                acc[5] += (double)cs.neq;
+                acc[6] += (double)cs.pi;
                 nfault += cs.fault ? 1u : 0u;
             }
         }
-        acc[0] += (double)rsum[0];
-        acc[1] += (double)rsum[1];
-        acc[2] += (double)rsum[2];
-        acc[4] += (double)rsum[3];
-        acc[5] += (double)rsum[4];
-        acc[6] += (double)rsum[5];
     }
     if (y0 < y1) store_row(y1 - 1);
     if (nfault) atomicAdd(faults, (unsigned long long)nfault);
@@ -697,16 +680,11 @@ __global__ __launch_bounds__(kBlock) void d2q9_fused2_kernel(
         th[k][1] = F32 ? R(a.thr_f[k][1]) : R(a.thr[k][1]);
     }
     auto level_of = [&](const CellSense<R>& cs) {
-        int level = 0;
+        LevelAcc lv;
         const R sv[3] = {cs.kl, cs.neq, cs.pi};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (a.mask & (1u << k)) {
-                const int l = (sv[k] > th[k][0]) + (sv[k] > th[k][1]);
-                level = l > level ? l : level;
-            }
-        }
-        return cs.fault ? uint8_t(0x82) : uint8_t(level);
+        for (int k = 0; k < 3; ++k) lv.add(sv[k], th[k][0], th[k][1]);
+        return cs.fault ? uint8_t(0x82) : uint8_t(lv.level());
     };
     auto store_cell = [&](int Y, const R (&d)[9], const CellSense<R>& cs) {
         const long long off = (long long)Y * nx + X;

@@ -47,10 +47,27 @@ lks::ExtArgs ext_args(const lks_config& c)
     return x;
 }
 
+// Thresholds the kernels compare the base sensors with: those of the sensors
+// in flag_mask, +INF for the others (a sensor compares false with +INF, NaN
+// included), so the kernels take every base sensor without a branch on the
+// mask.  The quasi-equilibrium sensor of the double distribution likewise.
+double flag_thr(const lks_config& c, int s, int j)
+{
+    return (c.flag_mask & (1u << s)) ? c.thr[s][j] : INFINITY;
+}
+double flag_thr_qe(const lks_config& c, int j)
+{
+    return (c.flag_mask & LKS_S_QE) ? c.thr_qe[j] : INFINITY;
+}
+
 int planes_of(const lks_config& c) { return base_planes(c) + __builtin_popcount(c.ext_mask); }
 size_t store_bytes(int dtype) { return dtype == LKS_F64 ? 8 : (dtype == LKS_F32 ? 4 : 2); }
 size_t sens_bytes(int dtype) { return dtype == LKS_F64 ? 8 : 4; }
-int wide_vec(int dtype) { return dtype == LKS_F64 ? 2 : 4; }
+// cells per thread of the D2Q9 cell kernels when the hint is 0: FP32 four
+// (16-byte accesses); FP64 two; 16-bit storage two, which leaves the kernel
+// room for three waves per SIMD instead of two (BF16 / FP16 at 8192^2:
+// 684 / 690 us per step against 705 / 716 with four cells)
+int wide_vec(int dtype) { return dtype == LKS_F32 ? 4 : 2; }
 
 // Launch shape of the D2Q9 cell kernels for a given vector width.
 lks::GridShape d2q9_shape(const lks_config& c, int vec)
@@ -151,14 +168,15 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
     a.dt = c.dt;
     a.dx = c.dx;
     a.rho0 = c.rho0;
-    std::memcpy(a.thr, c.thr, sizeof(a.thr));
+    for (int s = 0; s < LKS_MAX_SENSORS; ++s)
+        for (int j = 0; j < 2; ++j) a.thr[s][j] = flag_thr(c, s, j);
     a.mask = c.flag_mask;
     a.x = ext_args(c);
     a.model = c.model;
     a.cv = ddf(c) ? cv_of(c) : 0.0;
     a.prandtl = ddf(c) ? c.prandtl : 1.0;
-    a.thr_qe[0] = ddf(c) ? c.thr_qe[0] : 0.0;
-    a.thr_qe[1] = ddf(c) ? c.thr_qe[1] : 0.0;
+    a.thr_qe[0] = ddf(c) ? flag_thr_qe(c, 0) : INFINITY;
+    a.thr_qe[1] = ddf(c) ? flag_thr_qe(c, 1) : INFINITY;
     a.aux = nullptr;
     lks::d2q25_tile_shape(c.dtype, c.model, &a.tile_x, &a.tile_y);
     a.tiles_x = (c.nx + a.tile_x - 1) / a.tile_x;
@@ -316,13 +334,16 @@ void setup_ctx(lks_ctx* c, const lks_config& cfg, const lks_buffers& buf, hipStr
     a.L = lks::pop_layout(cfg.layout, c->Q, cfg.nx, cfg.ny);
     a.tau = cfg.tau;
     a.rho0 = cfg.rho0;
-    std::memcpy(a.thr, cfg.thr, sizeof(a.thr));
     a.mask = cfg.flag_mask;
     a.g = d2q9_shape(cfg, vec);
     a.inv_tau_f = (float)(1.0 / cfg.tau);
     a.rho0_f = (float)cfg.rho0;
-    for (int s = 0; s < LKS_MAX_SENSORS; ++s)
-        for (int k = 0; k < 2; ++k) a.thr_f[s][k] = (float)cfg.thr[s][k];
+    for (int s = 0; s < LKS_MAX_SENSORS; ++s) {
+        for (int k = 0; k < 2; ++k) {
+            a.thr[s][k] = flag_thr(cfg, s, k);
+            a.thr_f[s][k] = (float)a.thr[s][k];
+        }
+    }
     a.x = ext_args(cfg);
     // Non-temporal stores in the fused D2Q9 step when the two state buffers
     // exceed the 256 MB last-level cache: the next step's loads then come

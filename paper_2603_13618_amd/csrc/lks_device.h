@@ -238,6 +238,45 @@ __device__ __forceinline__ double kl_series(double x)
     return p;
 }
 
+// The D2Q9 cell update's first try: in FP32 the series truncated after
+// n = 5 for |x| <= 0.03 (relative truncation 2 x^4/30 < 5.4e-8), two
+// multiply-adds per population fewer than kl_series; cells with a larger
+// |x| take kl_phi.  On the smooth and shear-layer workloads every cell has
+// |x| < 0.02, so the fallback never runs there.  FP64 keeps kl_series.
+template <typename R> struct KlShortCut;
+template <> struct KlShortCut<float> { static constexpr float v = 0.03f; };
+template <> struct KlShortCut<double> { static constexpr double v = KlCut<double>::v; };
+__device__ __forceinline__ float kl_series_short(float x)
+{
+    float p = -1.0f / 20.0f;
+    p = p * x + 1.0f / 12.0f;
+    p = p * x + -1.0f / 6.0f;
+    p = p * x + 0.5f;
+    return p;
+}
+__device__ __forceinline__ double kl_series_short(double x) { return kl_series(x); }
+
+// Refinement level of a cell: per enabled sensor k, [s_k > t1_k] +
+// [s_k > t2_k], the maximum over k.  With t1 <= t2 (checked at creation, and
+// kept by the rounding to FP32) that maximum is 2 when some s_k > t2_k, else
+// 1 when some s_k > t1_k: the comparisons only OR lane masks, and one select
+// gives the level.  A NaN sensor compares false, as in the sum of the two.
+struct LevelAcc {
+    bool any1 = false, any2 = false;
+    template <typename R> __device__ __forceinline__ void add(R s, R t1, R t2)
+    {
+        any1 = any1 | (s > t1);
+        any2 = any2 | (s > t2);
+    }
+    __device__ __forceinline__ int level() const { return any2 ? 2 : (any1 ? 1 : 0); }
+};
+
+// Square root of a sensor norm: in FP32 the hardware instruction
+// (v_sqrt_f32, within 1 ulp; the correctly rounded library sequence adds
+// about 14 instructions per call), in FP64 the library's sqrt.
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+
 // phi(x) on either branch
 template <typename R>
 __device__ __forceinline__ R kl_phi(R x)

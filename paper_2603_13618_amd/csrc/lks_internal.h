@@ -54,7 +54,7 @@ struct D2Q9Args {
     PopLayout L;              // population planes
     double tau;
     double rho0;
-    double thr[4][2];
+    double thr[4][2];         // flag thresholds, +INF for sensors not in mask
     unsigned mask;
     GridShape g;
     // the same parameters rounded to FP32 on the host, so FP32 kernels keep
@@ -72,7 +72,7 @@ struct D2Q25Args {
     int bc_x, bc_y;           // 0 periodic, 1 outflow
     double mu, dt, dx;
     double rho0;
-    double thr[4][2];
+    double thr[4][2];         // flag thresholds, +INF for sensors not in mask
     unsigned mask;
     int tile_x, tile_y;       // cells per workgroup tile
     int tiles_x, tiles_y;
@@ -82,7 +82,7 @@ struct D2Q25Args {
     int model;
     double cv;                // C_v = R/(gamma - 1)
     double prandtl;           // Pr = tau1/tau2 (<= 1)
-    double thr_qe[2];         // thresholds of the quasi-equilibrium sensor
+    double thr_qe[2];         // flag thresholds of the quasi-equilibrium sensor (+INF if not in mask)
     // per-cell hand-over of the double distribution's f pass to its g pass:
     // [6][plane] of drho, ux, uy, T - 1, q_g (x, y) in the compute type
     void* aux;

@@ -213,7 +213,8 @@ class Lattice:
     then holds 50 planes, f then g, and sensors 5 planes, the fifth S_QE with
     thresholds thr_qe and flag bit S_QE).
     launch_steps: 2 runs two fused D2Q9 steps per launch (no extension
-    sensors; pairs need max_steps >= 2); the results are the same bits, and
+    sensors; pairs need max_steps >= 2); state, sensors, flags and fault
+    counts are the same bits (the per-step sums agree to FP64 rounding), and
     `state` follows the buffer that holds the current state.
     """
 

@@ -81,12 +81,13 @@ def test_fp64_matches_oracle(case):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_base_outputs_unchanged_by_the_extension(dtype):
+@pytest.mark.parametrize("n,ny", [(64, 64), (60, 50)])     # whole tiles, ragged
+def test_base_outputs_unchanged_by_the_extension(dtype, n, ny):
     f0, dt, dx = _riemann_state(64, 5, 1e-3)
-    d = torch.from_numpy(f0 - _ref_planes())
+    d = torch.from_numpy(np.ascontiguousarray(f0[:, :ny, :n]) - _ref_planes())
     outs = []
     for ext in (None, EXT):
-        lat = _lat(64, 64, dtype, 1e-3, dt, dx, (1, 1), ext=ext)
+        lat = _lat(n, ny, dtype, 1e-3, dt, dx, (1, 1), ext=ext)
         lat.restore(d)
         lat.step(2)
         torch.cuda.synchronize()

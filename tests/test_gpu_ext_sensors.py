@@ -117,15 +117,15 @@ def test_extension_changes_nothing_else(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_d2q25_extension_changes_nothing_else(dtype):
-    n = 96
-    rho, ux, uy, T, states = inputs.riemann_quadrants(n, n, seed=1)
+@pytest.mark.parametrize("n,ny", [(96, 96), (90, 84)])     # whole tiles, ragged
+def test_d2q25_extension_changes_nothing_else(dtype, n, ny):
+    rho, ux, uy, T, states = inputs.riemann_quadrants(n, ny, seed=1)
     dx = 1.0 / n
     dt = inputs.riemann_dt(states, dx)
     kw = dict(mu=1e-3, dt=dt, dx=dx, bc=(1, 1), max_steps=6, flag_mask=15,
               thr=np.array([[1e-7, 1e-6], [1e-4, 1e-3], [1e-3, 1e-2], [1e-3, 1e-2]]))
-    a = lks.Lattice(25, n, n, dtype, **kw)
-    b = lks.Lattice(25, n, n, dtype, ext=EXT25, **kw)
+    a = lks.Lattice(25, n, ny, dtype, **kw)
+    b = lks.Lattice(25, n, ny, dtype, ext=EXT25, **kw)
     for lat in (a, b):
         lat.init(rho, ux, uy, T)
         lat.step(6)

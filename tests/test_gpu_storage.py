@@ -40,13 +40,16 @@ def _state16(nx, ny, tdt, seed):
 
 
 @pytest.mark.parametrize("dtype,tdt", [("bf16", torch.bfloat16), ("f16", torch.float16)])
-@pytest.mark.parametrize("nx,ny,vec", [(1024, 40, 0), (100, 37, 2), (100, 37, 1), (6, 5, 0)])
+@pytest.mark.parametrize("nx,ny,vec", [(1024, 40, 0), (1024, 40, 4), (100, 37, 2), (100, 37, 1),
+                                       (6, 5, 0)])
 def test_store_is_rne_of_the_fp32_result(dtype, tdt, nx, ny, vec):
-    # vec: cells per thread (0 = the default, 4 where the row length allows)
+    # vec: cells per thread (0 = the default, 2 for 16-bit storage).  The FP32
+    # run takes the same launch shape: each thread adds its cells' sums before
+    # widening them to FP64, so equal sums need equal cells per thread.
     s16 = _state16(nx, ny, tdt, seed=5)
     thr = _thresholds(s16, nx, ny)
     a = lks.Lattice(9, nx, ny, dtype, tau=0.55, thr=thr, flag_mask=7, launch_vec=vec)
-    b = lks.Lattice(9, nx, ny, "f32", tau=0.55, thr=thr, flag_mask=7, launch_vec=vec)
+    b = lks.Lattice(9, nx, ny, "f32", tau=0.55, thr=thr, flag_mask=7, launch_vec=vec or 2)
     a.restore(s16)
     b.restore(s16.float())
     a.step(1)

@@ -112,6 +112,9 @@ def parse():
                    help="time two fused steps per launch (launch_steps = 2) against one, FP32 on "
                         "the 4096^2 and 8192^2 smooth fields (the default; kept for explicit use)")
     p.add_argument("--no-two-step", action="store_true", help="skip the two-steps-per-launch leg")
+    p.add_argument("--case3", action="store_true",
+                   help="also run the modified 2D Riemann problem No. 3 at the paper's 1024^2 "
+                        "to t = 0.85 (double distribution, FP32; about 196k steps)")
     p.add_argument("--regrid", action="store_true",
                    help="also time the regridding hand-off on the final flag map")
     p.add_argument("--layout", choices=["planes", "rows"], default="rows",
@@ -371,6 +374,8 @@ def main():
         out["adjoint"] = time_adjoint(torch, lks, inputs, workloads, dev, ev)
     if args.ext:
         out["ext"] = time_ext(torch, lks, inputs, workloads, dev, ev)
+    if args.case3:
+        out["case3"] = run_case3(torch, lks, inputs, dev, ev)
     if legs and not args.no_two_step:
         out["two_step"] = time_two_step(torch, lks, inputs, workloads, dev, ev)
     if regrid is not None:
@@ -630,6 +635,54 @@ def time_two_step(torch, lks, inputs, workloads, dev, ev, k=32, rounds=RUNS):
                            "speedup": round(med[0] / med[2], 3)}
         del lats, lat
         torch.cuda.empty_cache()
+    return res
+
+
+def run_case3(torch, lks, inputs, dev, ev, n=1024, mu=1e-3, gamma=1.4, prandtl=0.71, t_end=0.85):
+    """The paper's modified Riemann problem No. 3 (Sec. IV): air, mu = 1e-3,
+    CFL 0.01, outflow edges, from the initial quadrants to t_end, FP32 double
+    distribution.  Whole run timed with HIP events (sums reduced every 64
+    steps); the final state summarised: ranges, positivity faults, x <-> y
+    asymmetry, and the kinetic class-1 sensors against the macroscopic ones."""
+    import numpy as np
+    fields = inputs.riemann_case3(n)
+    dx = 1.0 / n
+    dt = inputs.cfl_dt(fields, dx, gamma)
+    steps = int(round(t_end / dt))
+    lat = lks.Lattice(25, n, n, "f32", mu=mu, dt=dt, dx=dx, bc=(1, 1), max_steps=64, model="ddf",
+                      gamma=gamma, prandtl=prandtl, layout=LAYOUT, device=dev)
+    lat.init(*fields)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record()
+    lat.step(steps - 1)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) * 1e-3
+    m = [x.clone() for x in lat.moments()]
+    lat.step(1)
+    mac = lat.macro_sensors(*m, mu=mu, lam=-(gamma - 1.0) * mu, kappa=gamma / (gamma - 1.0) * mu / prandtl,
+                            which=("tau", "qnsf"))
+    r, ux, uy, T = (x.double().cpu().numpy() for x in m)
+    s = lat.sensors.double().cpu().numpy()
+
+    def med(k, name):
+        q = mac[name].cpu().numpy()
+        keep = q > 1e-3 * q.max()
+        return round(float(np.median(s[k][keep] / q[keep])), 4)
+    res = {"workload": "modified 2D Riemann problem No. 3, D2Q25 double distribution FP32, air "
+                       f"(gamma={gamma}, Pr={prandtl}), mu={mu}, {n}x{n} outflow, CFL 0.01, t_end={t_end}",
+           "steps": steps, "s": round(t, 3), "MLUPS": round(n * n * (steps - 1) / t / 1e6, 1),
+           "us_per_step": round(t / (steps - 1) * 1e6, 2),
+           "rho": [round(float(r.min()), 4), round(float(r.max()), 4)],
+           "T": [round(float(T.min()), 4), round(float(T.max()), 4)],
+           "fault_cells_last_step": int((lat.flags >= 128).sum()),
+           "asymmetry_rho": float(np.abs(r - r.T).max() / r.max()),
+           "S_PI_over_tau_NS_median": med(2, "tau"), "S_Q_over_q_NSF_median": med(3, "qnsf"),
+           "sensor_p50_p99": {nm: [float(np.percentile(s[k][np.isfinite(s[k])], p)) for p in (50, 99)]
+                              for k, nm in enumerate(("S_KL", "S_NEQ", "S_PI", "S_Q", "S_QE"))}}
+    del lat
+    torch.cuda.empty_cache()
     return res
 
 

@@ -808,7 +808,12 @@ static uint8_t ddf_flag(const double* s, const double* thr, unsigned mask, int f
  *   SHEAR     |(1/mu)[(tr P/D) I - P]|, P = sum v v f^neq     (eq. sensor-S-kin)
  *   QH        |u . P|                                         (eq. sensor-qH-kin)
  *   QF        |sum v g^neq + sum v |v|^2/2 f^neq - u . P|      (eq. sensor-qF-kin-ryk)
- *   COMP, STRAIN: 0 (not defined for this model here).
+ *   COMP      sqrt(D)|tr P|/|2 mu + D lambda|                  (eq. sensor-C-kin)
+ *   STRAIN    |(1/2mu)[lambda/(D eta) tr(P) I - P]|_F          (eq. sensor-E-kin)
+ * with the model's second viscosity lambda = -(R/C_v) mu = -(gamma - 1) mu
+ * and bulk viscosity eta = (2/D - R/C_v) mu = (2 - gamma) mu (D = 2, R = 1;
+ * Sec. II.A.2, eqs. viscHeating and visc_bluk_1), the Chapman-Enskog limit
+ * that compression waves on this oracle reproduce (test_oracle_ddf_ext.py).
  * Omega = -(h - h*)/tau1 - (h* - h^eq)/tau2, tau1 = mu/(rho T), tau2 = tau1/Pr.
  * A positivity fault (any of f, f^eq, g, g^eq not > 0) gives +inf for the
  * five log/ratio sensors. */
@@ -875,8 +880,11 @@ static void ddf_cell_ext(const orc_rule* r, const double* f, const double* g, do
     s[ORC_X_SHEAR] = sqrt(sxx * sxx + 2.0 * sxy * sxy + syy * syy);
     s[ORC_X_QH] = sqrt(hx * hx + hy * hy);
     s[ORC_X_QF] = sqrt((qx - hx) * (qx - hx) + (qy - hy) * (qy - hy));
-    s[ORC_X_COMP] = 0.0;
-    s[ORC_X_STRAIN] = 0.0;
+    const double lambda = -mu / cv, eta = 2.0 * mu / D + lambda;
+    s[ORC_X_COMP] = sqrt((double)D) * fabs(tr) / fabs(2.0 * mu + D * lambda);
+    const double c = lambda / (D * eta);
+    const double exx = (c * tr - pxx) / (2.0 * mu), eyy = (c * tr - pyy) / (2.0 * mu), exy = -pxy / (2.0 * mu);
+    s[ORC_X_STRAIN] = sqrt(exx * exx + 2.0 * exy * exy + eyy * eyy);
 }
 
 /* extension sensors of n cells of a double-distribution state [50][n]:

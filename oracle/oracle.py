@@ -164,7 +164,7 @@ def ddf_moments(f, gamma=1.4, qe=False):
 def ddf_ext_sensors(f, mu, gamma=1.4, prandtl=0.71):
     """The extension sensors [len(EXT_NAMES), *shape] of a double-distribution
     state f [50, *shape] (g terms superposed, QE collision; COMP and STRAIN
-    are 0)."""
+    with the model's second viscosity -(gamma - 1) mu)."""
     f = _f64(f)
     n = f[0].size
     out = np.empty((len(EXT_NAMES),) + f.shape[1:])

@@ -444,6 +444,7 @@ def copy_ceiling(torch, lks, dev, ev, nbytes):
 
 EXT9 = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "comp", "strain")
 EXT25 = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf")
+EXTDDF = EXT25 + ("comp", "strain")
 
 
 def ext_lattices(lks, inputs, workloads, dev, steps):
@@ -472,11 +473,11 @@ def time_ext(torch, lks, inputs, workloads, dev, ev):
     single and the double distribution on D2Q25."""
     k = 40
     a, b = ext_lattices(lks, inputs, workloads, dev, k)
-    c = ddf_lattice(lks, inputs, workloads, dev, k, ext=EXT25)
+    c = ddf_lattice(lks, inputs, workloads, dev, k, ext=EXTDDF)
     res = {}
     for name, lat, nbytes in (("d2q9_4096_f32_ext9", a, 85 + 4 * len(EXT9)),
                               ("d2q25_2048_f32_ext8", b, 217 + 4 * len(EXT25)),
-                              ("d2q25_ddf_2048_f32_ext8", c, BYTES_F32_DDF + 4 * len(EXT25))):
+                              ("d2q25_ddf_2048_f32_ext10", c, BYTES_F32_DDF + 4 * len(EXTDDF))):
         warm_up(torch, lambda: lat.step(1))
         t = median_time(torch, ev, RUNS, lambda: lat.step(k)) / k
         cells = lat.nx * lat.ny
@@ -556,7 +557,7 @@ def time_d2q25(torch, ev, lat, k, name, kernel, bpl):
 def kernel_only(args, torch, lks, inputs, workloads, dev):
     """A short run of one of the other workloads (for profilers)."""
     if args.workload == "riemann2048-ddf-ext":
-        ddf_lattice(lks, inputs, workloads, dev, args.steps, ext=EXT25).step(args.steps)
+        ddf_lattice(lks, inputs, workloads, dev, args.steps, ext=EXTDDF).step(args.steps)
     elif args.workload.endswith("-ext"):
         a, b = ext_lattices(lks, inputs, workloads, dev, args.steps)
         (a if args.workload.startswith("smooth") else b).step(args.steps)

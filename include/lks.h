@@ -119,8 +119,12 @@ enum { LKS_S_KL = 1u, LKS_S_NEQ = 2u, LKS_S_PI = 4u, LKS_S_Q = 8u, LKS_S_QE = 16
  *                  planes after the five base planes) take the g terms
  *                  superposed and the QE collision as Omega: KN, HR, SIGMA_H,
  *                  SIGMA_HKL and ALPHA add the g form of each to the f form,
- *                  QF is |sum v g^neq + sum v |v|^2/2 f^neq - u . P|; SHEAR and
- *                  QH are those of f; COMP and STRAIN are not available. */
+ *                  QF is |sum v g^neq + sum v |v|^2/2 f^neq - u . P|; SHEAR,
+ *                  QH, COMP and STRAIN are those of f, COMP and STRAIN with
+ *                  the model's second viscosity lambda = -(gamma - 1) mu and
+ *                  bulk viscosity eta = 2 mu / D + lambda = (2 - gamma) mu
+ *                  (Sec. II.A.2, eqs. viscHeating and visc_bluk_1 with
+ *                  R/C_v = gamma - 1; Sec. III.A.2/4). */
 enum { LKS_MODEL_BGK = 0, LKS_MODEL_DDF = 1 };
 
 /* Extension sensors (bit k of ext_mask), the rest of Table I evaluated on the
@@ -145,10 +149,13 @@ enum { LKS_MODEL_BGK = 0, LKS_MODEL_DDF = 1 };
  *   SHEAR     |(1/mu)[(tr P / D) I - P]|_F        Sec. III.A.3, eq. sensor-S-kin
  *   QH        |u . P|                             Sec. III.A.5, eq. sensor-qH-kin
  *   QF        |q^neq - u . P|  (D2Q25 only)       Sec. III.A.7, eq. sensor-qF-kin-ryk (g = 0)
- *   COMP      sqrt(D) |tr P| / (2 mu)  (D2Q9 only) Sec. III.A.2, eq. sensor-C-kin
- *   STRAIN    |P|_F / (2 mu)  (D2Q9 only)         Sec. III.A.4, eq. sensor-E-kin
+ *   COMP      sqrt(D) |tr P| / |2 mu + D lambda|  Sec. III.A.2, eq. sensor-C-kin
+ *             (D2Q9: lambda = 0; double distribution: see LKS_MODEL_DDF)
+ *   STRAIN    |(1/2mu)[lambda/(D eta) tr(P) I - P]|_F, eta = 2 mu / D + lambda
+ *                                                 Sec. III.A.4, eq. sensor-E-kin
  * COMP and STRAIN divide by 2 mu + D lambda and eta, which vanish for the
- * monatomic D2Q25 gas (lambda = -mu); QF needs the energy flux D2Q9 lacks.
+ * monatomic D2Q25 BGK gas (lambda = -mu): not available there; QF needs the
+ * energy flux D2Q9 lacks.
  * Cells with a positivity fault get +inf for KN, HR, SIGMA_H, SIGMA_HKL and
  * ALPHA. */
 #define LKS_MAX_EXT 10
@@ -193,17 +200,19 @@ typedef struct {
     double gamma;         /* LKS_MODEL_DDF: adiabatic exponent, 1 < gamma < 2  */
     double prandtl;       /* LKS_MODEL_DDF: Prandtl number, 0 < Pr <= 1        */
     double thr_qe[2];     /* LKS_MODEL_DDF: (theta1 <= theta2) of S_QE         */
-    int32_t launch_nt;    /* stores of the fused D2Q9 step: 0 picks (the
-                             non-temporal hint when the two state buffers
-                             exceed the 256 MB last-level cache), 1 plain,
-                             2 non-temporal (a launch hint only: results are
-                             identical)                                        */
+    int32_t launch_nt;    /* population stores of the fused step: 0 picks
+                             (the non-temporal hint when the two state
+                             buffers exceed the 256 MB last-level cache),
+                             1 plain, 2 non-temporal (a launch hint only:
+                             results are identical).  D2Q9 every storage
+                             type; D2Q25 FP32 on grids of whole tiles      */
     int32_t launch_steps; /* fused D2Q9 steps per launch: 0 or 1 one, 2 two
                              (temporal blocking: the state crosses HBM once
                              per two steps; D2Q9 without extension sensors;
                              an odd last step of a reduction batch runs
-                             alone; a batch holds at most max_steps steps,
-                             so max_steps = 1 runs one step per launch).
+                             alone in the one-step kernel; a batch holds at
+                             most max_steps steps, so max_steps = 1 runs
+                             every step in the one-step kernel).
                              A launch hint: state, sensors, flags and the
                              fault count are the same bits and the per-step
                              FP64 sums agree to FP64 rounding (each cell's

@@ -213,6 +213,19 @@ __device__ __forceinline__ float vl_half<float>(float a, float b)
 }
 #endif
 
+// Population stores of the D2Q25 kernels, with the non-temporal hint (NTS)
+// when the two state buffers exceed the last-level cache: the next step's
+// loads come from HBM either way, and the hint keeps the written lines from
+// evicting the rows and halo lines other tiles are still to read (2048^2
+// single distribution: read traffic 612 -> 450 MB per step, 276.3 -> 269.6
+// us)
+template <bool NT, typename T>
+__device__ __forceinline__ void put_pop(T* p, T v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // f_face(j + 1/2) - f_face(j - 1/2) for the stencil q[-2..2] (q[2] = cell j),
 // upwind for velocity sign SIGN: the difference of the two upwind cells plus
 // the difference of their limited half slopes
@@ -262,8 +275,11 @@ __device__ __forceinline__ R advect(R o, const AdvScale<R>& sc, const R* t, cons
 // XCD's band); 2: plain row-major order.  Measured at 2048^2 (FP32 kernel
 // time per step, a 3-wave build of the single-distribution kernel): single
 // distribution 354 / 376 / 362 us for maps 1 / 0 / 2, double distribution
-// 799 / 808 / 877 us.  Shapes that do not divide into 8 bands use row-major
-// order.
+// 799 / 808 / 877 us.  Bands swept column by column were worse (read bytes
+// per step 913 and 1422 MB against 614 MB, 282 and 329 us against 277 us):
+// the x-halo of a 32-wide tile is two floats of each neighbour's 128-byte
+// rows, so horizontal neighbours must run close together in time.  Shapes
+// that do not divide into 8 bands use row-major order.
 #ifndef LKS_Q25_XCD_MAP
 #define LKS_Q25_XCD_MAP 1
 #endif
@@ -399,7 +415,7 @@ template <> struct Q25Waves<float> { static constexpr int v = LKS_Q25_WAVES > 0 
 // Unlike TileStage, only the threads with a halo cell load one: here that
 // keeps the kernel at 121 registers (four waves per SIMD) and measured 7 %
 // faster than the unconditional form.
-template <typename S, int TX, int TY, bool EXT = false, bool EDGE = true>
+template <typename S, int TX, int TY, bool EXT = false, bool EDGE = true, bool NTS = false>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Waves<S>::v))) void d2q25_kernel(D2Q25Args a, const typename Store<S>::raw* __restrict__ fin,
                                                    typename Store<S>::raw* __restrict__ fout,
                                                    typename Store<S>::real* __restrict__ sens,
@@ -539,7 +555,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(Q25Wave
             // collision, then the flux divergence (dimension by dimension,
             // upwind + van Leer)
             const R o = advect<R>(fma(B, deq - d, d), adv, t, rb, tx, d, ia, ib);
-            if (active) fout[i * a.L.pp + poff] = Store<S>::from_real(o);
+            if (active) put_pop<NTS>(fout + i * a.L.pp + poff, Store<S>::from_real(o));
         });
         if constexpr (g + 1 < 5) {
             write_group(std::integral_constant<int, g + 1>{});
@@ -664,7 +680,7 @@ template <> struct DdfWaves<float> { static constexpr int v = LKS_DDF_WAVES > 0 
 template <typename S> struct DdfGWaves { static constexpr int v = 1; };
 template <> struct DdfGWaves<float> { static constexpr int v = LKS_DDF_G_WAVES > 0 ? LKS_DDF_G_WAVES : 1; };
 
-template <typename S, int TX, int TY, bool EXT = false, bool EDGE = true>
+template <typename S, int TX, int TY, bool EXT = false, bool EDGE = true, bool NTS = false>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWaves<S>::v))) void d2q25_ddf_kernel(
     D2Q25Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ partials,
@@ -904,8 +920,15 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         xv[6] = sqrt(hx * hx + hy * hy);
         const R fx = qxo - hx, fy = qyo - hy;
         xv[7] = sqrt(fx * fx + fy * fy);
-        xv[8] = R(0);
-        xv[9] = R(0);
+        // compression and strain with the model's second viscosity lambda =
+        // -(R/C_v) mu and bulk viscosity eta = mu + lambda (D = 2; Sec. II.A.2,
+        // eq. visc_bluk_1): sqrt(D)|tr P| / |2 mu + D lambda| and
+        // |(1/2mu)[lambda/(D eta) tr(P) I - P]|_F
+        const R trp = pxx_p + pyy_p;
+        xv[8] = R(1.4142135623730951 / (2.0 * (a.mu - a.mu / a.cv))) * fabs(trp);
+        const R cl = R(-1.0 / (2.0 * (a.cv - 1.0))), i2mu = R(0.5 / a.mu);
+        const R exx = (cl * trp - pxx_p) * i2mu, eyy = (cl * trp - pyy_p) * i2mu, exy = -pxy_p * i2mu;
+        xv[9] = sqrt(exx * exx + R(2) * exy * exy + eyy * eyy);
     }
 
     // ---- pass 2: f' = f - A div - (dt/tau1)(f - f^eq) + (dt/tau1 - dt/tau2)(f* - f^eq),
@@ -928,7 +951,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const R dfs = w * (qfx * vx + qfy * vy) * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
         qe += fabs(dfs);
         const R o = advect<R>(fma(B12, dfs, fma(-B1, fneq, d)), adv, lds + i * T::kPlane, rb, tx, d, ia, ib);
-        if (active) fout[i * a.L.pp + poff] = Store<S>::from_real(o);
+        if (active) put_pop<NTS>(fout + i * a.L.pp + poff, Store<S>::from_real(o));
     });
     // g* - g^eq = w (q_g . v): its part of the QE sensor; g itself is updated
     // by d2q25_ddf_g_kernel from the cell state handed over here
@@ -996,7 +1019,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
 // g' = g - A div - (dt/tau1)(g - g^eq) + (dt/tau1 - dt/tau2)(g* - g^eq).
 // Splitting the step here keeps the f kernel within two waves per SIMD
 // without spilling registers.
-template <typename S, int TX, int TY, bool EDGE = true>
+template <typename S, int TX, int TY, bool EDGE = true, bool NTS = false>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfGWaves<S>::v))) void d2q25_ddf_g_kernel(D2Q25Args a,
                                                          const typename Store<S>::raw* __restrict__ fin,
                                                          typename Store<S>::raw* __restrict__ fout)
@@ -1068,7 +1091,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfGWav
             const R gneq = dg - gfac * (Tc * deq + tm1 * (w * rho0));
             const R dgs = w * (qgx * vx + qgy * vy);
             const R o = advect<R>(fma(B12, dgs, fma(-B1, gneq, dg)), adv, buf + ib * kStride, rb, tx, dg, ia, ib);
-            if (active) fout[(25 + i) * a.L.pp + poff] = Store<S>::from_real(o);
+            if (active) put_pop<NTS>(fout + (25 + i) * a.L.pp + poff, Store<S>::from_real(o));
         });
         if constexpr (g + 1 < 5) {
             st.template write<NG, NG * (g + 1)>(lds[(g + 1) & 1], gc, vh, vc);
@@ -1089,13 +1112,24 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
     if (!a.aux) return hipErrorInvalidValue;
-    // the same EDGE form with and without the extension sensors (as above)
+    // the same EDGE form with and without the extension sensors (as above);
+    // the non-temporal stores on whole FP32 tiles whose rows are whole
+    // 128-byte lines only (on the f kernel's 16-float rows they wrote 717
+    // instead of 614 MB per step at 2048^2)
     const bool whole = a.nx % TX == 0 && a.ny % TY == 0;
-    if (a.x.mask && whole)
+    constexpr bool kNT = std::is_same<S, float>::value && TX * sizeof(R) >= 128;
+    const bool nt = kNT && whole && a.nt_stores;
+    if (a.x.mask && nt)
+        d2q25_ddf_kernel<S, TX, TY, true, false, kNT><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (a.x.mask && whole)
         d2q25_ddf_kernel<S, TX, TY, true, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     else if (a.x.mask)
         d2q25_ddf_kernel<S, TX, TY, true, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (nt)
+        d2q25_ddf_kernel<S, TX, TY, false, false, kNT><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     else if (whole)
         d2q25_ddf_kernel<S, TX, TY, false, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
@@ -1110,7 +1144,11 @@ static hipError_t launch_ddf_tile(const D2Q25Args& a, const void* fin, void* fou
     ag.tiles_x = (a.nx + GX - 1) / GX;
     ag.tiles_y = (a.ny + GY - 1) / GY;
     ag.nblocks = ag.tiles_x * ag.tiles_y;
-    if (a.nx % GX == 0 && a.ny % GY == 0)
+    const bool gwhole = a.nx % GX == 0 && a.ny % GY == 0;
+    constexpr bool kGNT = std::is_same<S, float>::value && GX * sizeof(R) >= 128;
+    if (kGNT && gwhole && a.nt_stores)
+        d2q25_ddf_g_kernel<S, GX, GY, false, kGNT><<<dim3(ag.nblocks), dim3(GX * GY), 0, s>>>(ag, (const raw*)fin, (raw*)fout);
+    else if (gwhole)
         d2q25_ddf_g_kernel<S, GX, GY, false><<<dim3(ag.nblocks), dim3(GX * GY), 0, s>>>(ag, (const raw*)fin, (raw*)fout);
     else
         d2q25_ddf_g_kernel<S, GX, GY><<<dim3(ag.nblocks), dim3(GX * GY), 0, s>>>(ag, (const raw*)fin, (raw*)fout);
@@ -1125,13 +1163,22 @@ static hipError_t launch_tile(const D2Q25Args& a, const void* fin, void* fout, v
     using R = typename Store<S>::real;
     if (a.tile_x != TX || a.tile_y != TY) return hipErrorInvalidValue;
     // with and without the extension sensors the same EDGE form runs, so the
-    // base outputs stay the same bits
+    // base outputs stay the same bits; the non-temporal stores on whole FP32
+    // tiles of whole 128-byte rows only
     const bool whole = a.nx % TX == 0 && a.ny % TY == 0;
-    if (a.x.mask && whole)
+    constexpr bool kNT = std::is_same<S, float>::value && TX * sizeof(R) >= 128;
+    const bool nt = kNT && whole && a.nt_stores;
+    if (a.x.mask && nt)
+        d2q25_kernel<S, TX, TY, true, false, kNT><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (a.x.mask && whole)
         d2q25_kernel<S, TX, TY, true, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     else if (a.x.mask)
         d2q25_kernel<S, TX, TY, true, true><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
+            a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
+    else if (nt)
+        d2q25_kernel<S, TX, TY, false, false, kNT><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(
             a, (const raw*)fin, (raw*)fout, (R*)sens, flags, partials, faults);
     else if (whole)
         d2q25_kernel<S, TX, TY, false, false><<<dim3(a.nblocks), dim3(TX * TY), 0, s>>>(

@@ -595,9 +595,10 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
 // steps.  The loads of raw rows q + 1 and q + 2 are in flight while row q is
 // used.  kSweepH = 16 rows per wave: short strips give more independent waves,
 // which hides latency better than the shorter ring of tall strips saves bytes.
-// TWO = false: one step (the odd step of a run), stored.  Each cell's
-// arithmetic is cell_update, as in the one-step kernels, so the results are
-// bit-identical.
+// Each cell's arithmetic is cell_update, as in the one-step kernels, so the
+// results are bit-identical to two one-step launches.  A step that has no
+// partner (an odd batch end) runs in the one-step kernel: this sweep with a
+// single step measured 362.8 against 233.2 us at 4096^2.
 constexpr int kSweepW = kWave - 4;
 constexpr int kSweepH = 16;
 
@@ -651,7 +652,7 @@ __device__ __forceinline__ void gather_pull(R (&d)[9], const R (&prev2)[9], cons
     });
 }
 
-template <typename S, bool TWO>
+template <typename S>
 __global__ __launch_bounds__(kBlock) void d2q9_fused2_kernel(
     D2Q9Args a, const typename Store<S>::raw* __restrict__ fin, typename Store<S>::raw* __restrict__ fout,
     typename Store<S>::real* __restrict__ sens, uint8_t* __restrict__ flags, double* __restrict__ part_a,
@@ -716,28 +717,26 @@ __global__ __launch_bounds__(kBlock) void d2q9_fused2_kernel(
     unsigned nfault = 0;
 
     if (has) {
-        // raw rows qs .. qe; step A on rows qs + 1 .. qe - 1, step B (TWO) on Yb .. Ye - 1
-        const int qs = Yb - (TWO ? 2 : 1), qe = Ye + (TWO ? 1 : 0);
+        // raw rows qs .. qe; step A on rows qs + 1 .. qe - 1, step B on Yb .. Ye - 1
+        const int qs = Yb - 2, qe = Ye + 1;
         R prev2[9], prev[9], cur[9], nxt[9] = {}, nxt2[9] = {};
         R aprev3[9], aprev2[9], aprev[9];
         load_row(qs, prev2);
         load_row(qs + 1, prev);
         load_row(qs + 2, cur);
         if (qs + 3 <= qe) load_row(qs + 3, nxt);
-        const int qend = qe + (TWO ? 1 : 0);
+        const int qend = qe + 1;
         for (int q = qs + 2; q <= qend; ++q) {
             if (q + 2 <= qe) load_row(q + 2, nxt2);
-            if constexpr (TWO) {
-                // ---- step B on row q - 3 (step A rows q - 4, q - 3, q - 2 of earlier iterations)
-                if (q >= qs + 5) {
-                    R e[9];
-                    gather_pull(e, aprev3, aprev2, aprev);
-                    R drho2, jx2, jy2;
-                    const CellSense<R> cs2 = cell_update<R, true, true>(e, rho0, inv_tau, drho2, jx2, jy2);
-                    if (own_col) {
-                        store_cell(q - 3, e, cs2);
-                        add_sums(acc_b, nfault, drho2, jx2, jy2, cs2);
-                    }
+            // ---- step B on row q - 3 (step A rows q - 4, q - 3, q - 2 of earlier iterations)
+            if (q >= qs + 5) {
+                R e[9];
+                gather_pull(e, aprev3, aprev2, aprev);
+                R drho2, jx2, jy2;
+                const CellSense<R> cs2 = cell_update<R, true, true>(e, rho0, inv_tau, drho2, jx2, jy2);
+                if (own_col) {
+                    store_cell(q - 3, e, cs2);
+                    add_sums(acc_b, nfault, drho2, jx2, jy2, cs2);
                 }
             }
             if (q <= qe) {
@@ -748,15 +747,11 @@ __global__ __launch_bounds__(kBlock) void d2q9_fused2_kernel(
                 const CellSense<R> cs = cell_update<R, true, true>(d, rho0, inv_tau, drho, jx, jy);
                 const bool own_a = own_col && ya >= Yb && ya < Ye;
                 if (own_a) add_sums(acc_a, nfault, drho, jx, jy, cs);
-                if constexpr (TWO) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        aprev3[i] = aprev2[i];
-                        aprev2[i] = aprev[i];
-                        aprev[i] = Store<S>::to_real(Store<S>::from_real(d[i]));
-                    }
-                } else {
-                    if (own_a) store_cell(ya, d, cs);
+                for (int i = 0; i < 9; ++i) {
+                    aprev3[i] = aprev2[i];
+                    aprev2[i] = aprev[i];
+                    aprev[i] = Store<S>::to_real(Store<S>::from_real(d[i]));
                 }
             }
 #pragma unroll
@@ -769,27 +764,20 @@ __global__ __launch_bounds__(kBlock) void d2q9_fused2_kernel(
         }
     }
     block_sums(acc_a, part_a + (long long)blockIdx.x * kNsums);
-    if constexpr (TWO) {
-        __syncthreads();                          // block_sums' LDS is read before it is written again
-        block_sums(acc_b, part_b + (long long)blockIdx.x * kNsums);
-    }
+    __syncthreads();                              // block_sums' LDS is read before it is written again
+    block_sums(acc_b, part_b + (long long)blockIdx.x * kNsums);
     if (nfault) atomicAdd(faults, (unsigned long long)nfault);
 }
 
 template <typename S>
-static hipError_t launch_two(const D2Q9Args& a, bool two, const void* fin, void* fout, void* sens,
-                             uint8_t* flags, double* part_a, double* part_b, unsigned long long* faults,
-                             hipStream_t st)
+static hipError_t launch_two(const D2Q9Args& a, const void* fin, void* fout, void* sens, uint8_t* flags,
+                             double* part_a, double* part_b, unsigned long long* faults, hipStream_t st)
 {
     using raw = typename Store<S>::raw;
     using R = typename Store<S>::real;
     const dim3 grid((unsigned)d2q9_two_blocks(sizeof(raw) == 8 ? 0 : 1, a.nx, a.ny)), block(kBlock);
-    if (two)
-        d2q9_fused2_kernel<S, true><<<grid, block, 0, st>>>(a, (const raw*)fin, (raw*)fout, (R*)sens, flags,
-                                                            part_a, part_b, faults);
-    else
-        d2q9_fused2_kernel<S, false><<<grid, block, 0, st>>>(a, (const raw*)fin, (raw*)fout, (R*)sens, flags,
-                                                             part_a, part_b, faults);
+    d2q9_fused2_kernel<S><<<grid, block, 0, st>>>(a, (const raw*)fin, (raw*)fout, (R*)sens, flags, part_a,
+                                                  part_b, faults);
     return hipGetLastError();
 }
 
@@ -802,15 +790,15 @@ int d2q9_two_blocks(int dtype, int nx, int ny)
     return (int)((waves + kBlock / kWave - 1) / (kBlock / kWave));
 }
 
-hipError_t launch_d2q9_two(int dtype, const D2Q9Args& a, bool two, const void* fin, void* fout, void* sens,
+hipError_t launch_d2q9_two(int dtype, const D2Q9Args& a, const void* fin, void* fout, void* sens,
                            uint8_t* flags, double* part_a, double* part_b, unsigned long long* faults,
                            hipStream_t s)
 {
     switch (dtype) {
-    case 0: return launch_two<double>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
-    case 1: return launch_two<float>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
-    case 2: return launch_two<bf16_t>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
-    case 3: return launch_two<f16_t>(a, two, fin, fout, sens, flags, part_a, part_b, faults, s);
+    case 0: return launch_two<double>(a, fin, fout, sens, flags, part_a, part_b, faults, s);
+    case 1: return launch_two<float>(a, fin, fout, sens, flags, part_a, part_b, faults, s);
+    case 2: return launch_two<bf16_t>(a, fin, fout, sens, flags, part_a, part_b, faults, s);
+    case 3: return launch_two<f16_t>(a, fin, fout, sens, flags, part_a, part_b, faults, s);
     default: return hipErrorInvalidValue;
     }
 }

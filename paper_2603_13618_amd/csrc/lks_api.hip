@@ -113,8 +113,11 @@ const char* validate_config(const lks_config* c)
     if (c->dtype == LKS_F64 && c->launch_vec == 4) return "launch_vec 4 is not available for F64";
     if (c->ext_reserved != 0) return "ext_reserved must be 0";
     const unsigned all_ext = (1u << LKS_MAX_EXT) - 1u;
+    // QF needs the energy flux D2Q9 lacks; COMP and STRAIN divide by the
+    // bulk viscosity, zero for the monatomic D2Q25 BGK gas
     const unsigned valid_ext = c->lattice == LKS_D2Q9 ? all_ext & ~(unsigned)LKS_X_QF
-                                                      : all_ext & ~(unsigned)(LKS_X_COMP | LKS_X_STRAIN);
+                             : c->model == LKS_MODEL_DDF ? all_ext
+                                                          : all_ext & ~(unsigned)(LKS_X_COMP | LKS_X_STRAIN);
     if (c->ext_mask & ~valid_ext) return "ext_mask names a sensor this lattice does not have";
     if (c->model != LKS_MODEL_BGK && c->model != LKS_MODEL_DDF) return "model must be BGK or DDF";
     if (c->layout != LKS_LAYOUT_PLANES && c->layout != LKS_LAYOUT_ROWS) return "layout must be PLANES or ROWS";
@@ -178,6 +181,7 @@ lks::D2Q25Args d2q25_args(const lks_config& c)
     a.thr_qe[0] = ddf(c) ? flag_thr_qe(c, 0) : INFINITY;
     a.thr_qe[1] = ddf(c) ? flag_thr_qe(c, 1) : INFINITY;
     a.aux = nullptr;
+    a.nt_stores = 0;
     lks::d2q25_tile_shape(c.dtype, c.model, &a.tile_x, &a.tile_y);
     a.tiles_x = (c.nx + a.tile_x - 1) / a.tile_x;
     a.tiles_y = (c.ny + a.tile_y - 1) / a.tile_y;
@@ -357,6 +361,7 @@ void setup_ctx(lks_ctx* c, const lks_config& cfg, const lks_buffers& buf, hipStr
                 : (2.0 * c->Q * (double)c->n * (double)sb > 256.0 * (1 << 20) ? 1 : 0);
     c->a25 = d2q25_args(cfg);
     c->a25.aux = aux;
+    c->a25.nt_stores = a.nt_stores;
     c->nblocks = cfg.lattice == LKS_D2Q25 ? c->a25.nblocks : a.g.nblocks;
     c->nblocks2 = cfg.launch_steps == 2 ? lks::d2q9_two_blocks(cfg.dtype, cfg.nx, cfg.ny) : 0;
     // as many steps per reduction launch as the partials area holds for the
@@ -367,8 +372,8 @@ void setup_ctx(lks_ctx* c, const lks_config& cfg, const lks_buffers& buf, hipStr
     if (k > kMaxChunk) k = kMaxChunk;
     if (k > cfg.max_steps) k = cfg.max_steps;
     // two steps per launch pair the steps of one reduction batch: an even
-    // batch leaves no step to the sweep kernel's one-step form but the odd
-    // last one of a call
+    // batch pairs all of them, and only the odd last step of a call runs
+    // alone (in the one-step kernel)
     if (cfg.launch_steps == 2 && k > 1) k &= ~1LL;
     c->chunk = (int)(k < 1 ? 1 : k);
 }
@@ -384,21 +389,22 @@ lks_status step_impl(lks_ctx* c, int32_t nsteps, int32_t fused)
     if (c->cfg.ext_mask && !fused)
         return fail(c, LKS_EUNSUPPORTED, "extension sensors are computed by the fused step only");
     const lks::D2Q9Args& a = c->a9;
-    const bool two = fused && c->nblocks2 > 0;
-    const int nb = two ? c->nblocks2 : c->nblocks;
     int done = 0;
     while (done < nsteps) {
-        const int m = (nsteps - done) < c->chunk ? (nsteps - done) : c->chunk;
-        for (int s = 0; two && s < m;) {
-            // two steps per launch; an odd last step of the batch takes one
+        int m = (nsteps - done) < c->chunk ? (nsteps - done) : c->chunk;
+        // two steps per launch: the batch takes whole pairs; a step without a
+        // partner (the odd end of a call, or batches of one) is a batch of
+        // its own in the one-step kernel
+        const bool two = fused && c->nblocks2 > 0 && m >= 2;
+        if (two) m &= ~1;
+        const int nb = two ? c->nblocks2 : c->nblocks;
+        for (int s = 0; two && s < m; s += 2) {
             double* pa = c->partials + (size_t)s * nb * lks::kNsumsHost;
-            const bool pair = s + 1 < m;
-            hipError_t e = lks::launch_d2q9_two(c->cfg.dtype, a, pair, c->buf.pop[c->cur], c->buf.pop[1 - c->cur],
+            hipError_t e = lks::launch_d2q9_two(c->cfg.dtype, a, c->buf.pop[c->cur], c->buf.pop[1 - c->cur],
                                                 c->buf.sensors, c->buf.flags, pa,
                                                 pa + (size_t)nb * lks::kNsumsHost, c->faults, c->stream);
             if (lks_status st = hip_check(c, e, "step kernel")) return st;
             c->cur = 1 - c->cur;
-            s += pair ? 2 : 1;
         }
         for (int s = 0; !two && s < m; ++s) {
             double* part = c->partials + (size_t)s * nb * lks::kNsumsHost;

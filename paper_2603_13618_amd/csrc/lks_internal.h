@@ -86,6 +86,7 @@ struct D2Q25Args {
     // per-cell hand-over of the double distribution's f pass to its g pass:
     // [6][plane] of drho, ux, uy, T - 1, q_g (x, y) in the compute type
     void* aux;
+    int nt_stores;            // non-temporal population stores (large states)
 };
 constexpr int kDdfAux = 6;
 
@@ -96,9 +97,9 @@ enum Pass { kFused = 0, kStream = 1, kSense = 2, kCollide = 3 };
 hipError_t launch_d2q9(int dtype, int pass, const D2Q9Args& a, const void* fin, void* fout,
                        void* sens, uint8_t* flags, double* partials,
                        unsigned long long* faults, hipStream_t s);
-// two fused D2Q9 steps per launch (two = false: one step, same strips); the
-// sums of the first step go to part_a, of the second to part_b
-hipError_t launch_d2q9_two(int dtype, const D2Q9Args& a, bool two, const void* fin, void* fout, void* sens,
+// two fused D2Q9 steps per launch; the sums of the first step go to part_a,
+// of the second to part_b
+hipError_t launch_d2q9_two(int dtype, const D2Q9Args& a, const void* fin, void* fout, void* sens,
                            uint8_t* flags, double* part_a, double* part_b, unsigned long long* faults,
                            hipStream_t s);
 // workgroups of one launch_d2q9_two launch

@@ -221,9 +221,10 @@ def test_ddf_api_limits():
     with pytest.raises(lks.LksError) as e:
         _lattice(8, 8, "bf16", 1e-3, 1e-3, 0.1, (1, 1))
     assert e.value.status == 6
-    with pytest.raises(lks.LksError) as e:      # not defined for this model
-        lks.Lattice(25, 8, 8, "f32", mu=1e-3, dt=1e-3, dx=0.1, model="ddf", ext=["strain"])
+    with pytest.raises(lks.LksError) as e:      # no bulk viscosity on the monatomic BGK gas
+        lks.Lattice(25, 8, 8, "f32", mu=1e-3, dt=1e-3, dx=0.1, ext=["strain"])
     assert e.value.status == 1
+    lks.Lattice(25, 8, 8, "f32", mu=1e-3, dt=1e-3, dx=0.1, model="ddf", ext=["strain"])
     lat = _lattice(8, 8, "f32", 1e-3, 1e-3, 0.1, (1, 1))
     assert lat.pop[0].shape == (50, 8, 8) and lat.sensors.shape == (5, 8, 8)
     u = np.ones((8, 8))

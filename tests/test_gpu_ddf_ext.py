@@ -8,7 +8,8 @@ dissipation, whose oracle form is the literal difference of O(1) H values
 shared FP32 state: each sensor within a few times its measured FP32 floor
 (FP32_BARS); flags of extension sensors bit-exact outside the threshold band;
 switching the extension on changes neither the state nor the base sensors
-(bit for bit).  Compression and strain are not available on this model.
+(bit for bit).  Compression and strain take the model's second viscosity
+-(gamma - 1) mu (Sec. II.A.2, eq. visc_bluk_1).
 """
 import numpy as np
 import pytest
@@ -23,13 +24,15 @@ pytestmark = pytest.mark.gpu
 
 GAMMA, PR = 1.4, 0.71
 CV = 1.0 / (GAMMA - 1.0)
-EXT = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf")
+EXT = ("kn", "hr", "sigma_h", "sigma_hkl", "alpha", "shear", "qh", "qf", "comp", "strain")
 LITERAL_H = ("hr", "sigma_h")
 # FP32 floors measured on a 128^2 Riemann state, one step from a shared FP32
 # state: kn 1.6e-6, hr 7.9e-6, sigma_h 1.9e-6, sigma_hkl 2.0e-6, alpha 4.6e-6,
-# shear 9.3e-7, qh 2.5e-6, qf 2.5e-6; the bars are about four times them
+# shear 9.3e-7, qh 2.5e-6, qf 2.5e-6, comp 7.0e-6, strain 6.9e-6 (both built
+# on tr P, a sum of two stress components that largely cancel where the flow
+# shears); the bars are about four times them
 FP32_BARS = {"kn": 7e-6, "hr": 3e-5, "sigma_h": 8e-6, "sigma_hkl": 8e-6, "alpha": 2e-5,
-             "shear": 4e-6, "qh": 1e-5, "qf": 1e-5}
+             "shear": 4e-6, "qh": 1e-5, "qf": 1e-5, "comp": 3e-5, "strain": 3e-5}
 
 
 def _ref_planes(rho0=1.0):
@@ -147,8 +150,11 @@ def test_flags_of_extension_sensors():
 
 
 def test_ddf_extension_limits():
+    # compression and strain exist on the double distribution, not on the
+    # monatomic single distribution
     with pytest.raises(lks.LksError):
-        _lat(8, 8, "f32", 1e-3, 1e-3, 0.1, (1, 1), ext=["comp"])
+        lks.Lattice(25, 8, 8, "f32", mu=1e-3, dt=1e-3, dx=0.1, ext=["comp"])
+    assert _lat(8, 8, "f32", 1e-3, 1e-3, 0.1, (1, 1), ext=["comp", "strain"]).sensors.shape == (7, 8, 8)
     lat = _lat(8, 8, "f32", 1e-3, 1e-3, 0.1, (1, 1), ext=["kn", "qf"])
     assert lat.sensors.shape == (7, 8, 8)
     assert lat.ext("qf").data_ptr() == lat.sensors[6].data_ptr()

@@ -185,6 +185,29 @@ __device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& 
     sfor25<5>([&](auto ac) { e.template group<decltype(ac)::value>(use); });
 }
 
+// class of |v|^2 of population (a, b) on GH5 x GH5: 0 centre, 1 one inner
+// abscissa, 2 one outer, 3 two inner, 4 inner and outer, 5 two outer
+__device__ __forceinline__ constexpr int v2_class(int a, int b)
+{
+    const int p = a == 2 ? 0 : (a == 1 || a == 3) ? 1 : 2;
+    const int q = b == 2 ? 0 : (b == 1 || b == 3) ? 1 : 2;
+    return p == 0 ? q : q == 0 ? p : p + q + 1;
+}
+
+// pairwise (tree) sum of a register array: rounding error O(log N) instead
+// of O(N) terms deep
+template <typename R, int N>
+__device__ __forceinline__ R pairwise_sum(R (&v)[N])
+{
+#pragma unroll
+    for (int len = N; len > 1; len = (len + 1) / 2) {
+#pragma unroll
+        for (int k = 0; k < len / 2; ++k) v[k] = v[2 * k] + v[2 * k + 1];
+        if (len % 2) v[len / 2] = v[len - 1];
+    }
+    return v[0];
+}
+
 // half van Leer slope ab/(a+b) for same-sign a, b, else 0
 template <typename R>
 __device__ __forceinline__ R vl_half(R a, R b)
@@ -759,7 +782,14 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     // ---- moments: sum d, sum v d, sum |v|^2 d of f and sum dg of g
     const R rho0 = R(a.rho0);
     const R cv = R(a.cv);
-    R drho = R(0), jx = R(0), jy = R(0), m2 = R(0), dg0 = R(0);
+    // The energy moments m2 = sum |v|^2 d and dg0 = sum dg are summed with
+    // short rounding chains: m2 over the five classes of |v|^2 (four or eight
+    // populations each), dg0 pairwise.  S_KL's largest term, sum g^neq below,
+    // is a small difference of them (single-step FP32 error of S_KL on the
+    // 128^2 Riemann quadrants: 1.2e-5 with plain running sums, about 6e-6
+    // this way in a float emulation)
+    R drho = R(0), jx = R(0), jy = R(0);
+    R sc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, eg[25];
     sfor25<25>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ia = i / 5, ib = i % 5;
@@ -767,9 +797,12 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         drho += v;
         if (ia != 2) jx += R(gh5_xi(ia)) * v;
         if (ib != 2) jy += R(gh5_xi(ib)) * v;
-        m2 += R(gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) * v;
-        dg0 += gc[i];
+        sc[v2_class(ia, ib)] += v;
+        eg[i] = gc[i];
     });
+    constexpr double x3 = gh5_xi(3) * gh5_xi(3), x4 = gh5_xi(4) * gh5_xi(4);
+    const R m2 = fma(R(2 * x4), sc[5], fma(R(x3 + x4), sc[4], fma(R(2 * x3), sc[3], fma(R(x4), sc[2], R(x3) * sc[1]))));
+    const R dg0 = pairwise_sum(eg);
     const R rho = rho0 + drho;
     const R irho = rcp(rho);
     const R ux = jx * irho, uy = jy * irho;
@@ -780,7 +813,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     const R gfac = cv - R(1);                              // g^eq = (C_v - 1) T f^eq
 
     // ---- pass 1: non-equilibrium parts of f and g (sensors, heat fluxes)
-    R klf = R(0), klg = R(0), gsum = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0),
+    // sum g^neq = sum g - (C_v - 1) T rho, with T from the total energy:
+    // (dg0 - (C_v - 1)(m2/2 - rho |u|^2/2)) / C_v, the same value as summing
+    // the 25 g^neq_i, without the rounding of the equilibrium terms
+    const R gsum = fma(-gfac, fma(R(0.5), m2, -(R(0.5) * rho) * fma(ux, ux, uy * uy)), dg0) * R(1.0 / a.cv);
+    R klf = R(0), klg = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0),
       qy = R(0), qfx = R(0), qfy = R(0), qgx = R(0), qgy = R(0);
     // positivity (f, f^eq, g, g^eq > 0) and the reach of the KL series, per
     // population (lane masks)
@@ -801,7 +838,6 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const R y = gneq * rcp(geq);
         klf += (fneq * x) * kl_series_short(x);
         klg += (gneq * y) * kl_series_short(y);
-        gsum += gneq;
         nonpos = nonpos || !(feq > R(0)) || !(geq > R(0)) || !(x > R(-1)) || !(y > R(-1));
         far = far || !(fabs(x) <= KlShortCut<R>::v) || !(fabs(y) <= KlShortCut<R>::v);
         neq += fabs(fneq) + fabs(gneq);
@@ -820,9 +856,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         qgx += cx * gneq;
         qgy += cy * gneq;
     });
-    if (far) {
+    if (far && !nonpos) {
         // rare: some population far from equilibrium (or NaN): the closed
-        // form, one population at a time
+        // form, one population at a time.  Cells with a positivity fault
+        // skip it: their S_KL is +inf whatever the sums (on the paper's
+        // supersonic Riemann problem No. 3 that is half of the cells)
         klf = R(0);
         klg = R(0);
         sfor25<25>([&](auto ic) {

@@ -146,7 +146,8 @@ def test_fp32_single_step_from_shared_state(orc):
         e = maxnorm(lat.sensors[k], ref["sens"][k])
         print("sensor", k, f"{e:.2e}", flush=True)
         es.append(e)
-    assert max(es) <= 3e-5
+    # measured: S_KL 5.0e-6, S_NEQ 2.5e-6, S_PI 2.4e-6, S_Q 2.7e-6, S_QE 2.6e-6
+    assert max(es) <= 1e-5
     assert maxnorm(_dev(orc, _full(orc, lat)), _dev(orc, ref["f"])) <= 1e-5
     bad, excl = flags_outside_band(lat.flags, ref["flags"], ref["sens"], THR5, MASK,
                                    [max(e, 1e-6) for e in es])

@@ -112,6 +112,9 @@ def parse():
                    help="time two fused steps per launch (launch_steps = 2) against one, FP32 on "
                         "the 4096^2 and 8192^2 smooth fields (the default; kept for explicit use)")
     p.add_argument("--no-two-step", action="store_true", help="skip the two-steps-per-launch leg")
+    p.add_argument("--fp64", action="store_true",
+                   help="also time the FP64 forms: D2Q9 on the 4096^2 smooth field and the D2Q25 "
+                        "double distribution on the 2048^2 Riemann quadrants")
     p.add_argument("--case3", action="store_true",
                    help="also run the modified 2D Riemann problem No. 3 at the paper's 1024^2 "
                         "to t = 0.85 (double distribution, FP32; about 196k steps)")
@@ -374,6 +377,8 @@ def main():
         out["adjoint"] = time_adjoint(torch, lks, inputs, workloads, dev, ev)
     if args.ext:
         out["ext"] = time_ext(torch, lks, inputs, workloads, dev, ev)
+    if args.fp64:
+        out["fp64"] = time_fp64(torch, lks, inputs, workloads, dev, ev)
     if args.case3:
         out["case3"] = run_case3(torch, lks, inputs, dev, ev)
     if legs and not args.no_two_step:
@@ -636,6 +641,49 @@ def time_two_step(torch, lks, inputs, workloads, dev, ev, k=32, rounds=RUNS):
                            "speedup": round(med[0] / med[2], 3)}
         del lats, lat
         torch.cuda.empty_cache()
+    return res
+
+
+def time_fp64(torch, lks, inputs, workloads, dev, ev):
+    """FP64 storage and arithmetic: the fused D2Q9 step on the 4096^2 smooth
+    field (whole steps and the kernel alone) and the double distribution on
+    the 2048^2 Riemann quadrants (whole steps), medians of RUNS."""
+    res = {}
+    wl = workloads.SMOOTH_4096
+    n = wl["nx"]
+    rho, ux, uy = inputs.smooth_random(n, seed=wl["seed"], cutoff=wl["cutoff"])
+    lat = lks.Lattice(9, n, n, "f64", tau=wl["tau"], thr=wl["thr"], flag_mask=wl["flag_mask"], max_steps=32,
+                      layout=LAYOUT, device=dev)
+    lat.init(rho, ux, uy)
+    warm_up(torch, lambda: lat.step(1))
+    k = 16
+    t = median_time(torch, ev, RUNS, lambda: lat.step(k)) / k
+    src, dst = lat.pop[lat.current()[0]], lat.pop[1 - lat.current()[0]]
+
+    def alone():
+        for r in range(k):
+            lat.step_from(src, dst) if r % 2 == 0 else lat.step_from(dst, src)
+    tk = median_time(torch, ev, RUNS, alone) / k
+    res["d2q9_f64_4096"] = {"MLUPS": round(n * n / t / 1e6, 1), "us_per_step": round(t * 1e6, 1),
+                            "kernel_us": round(tk * 1e6, 1), "bytes_per_lup": 169,
+                            "GBps_model": round(169 * n * n / tk / 1e9, 1)}
+    del lat
+    torch.cuda.empty_cache()
+    wq = workloads.RIEMANN_2048_DDF
+    n = wq["nx"]
+    r, u, v, T, states = inputs.riemann_quadrants(n, seed=wq["seed"])
+    dx = 1.0 / n
+    lat = lks.Lattice(25, n, n, "f64", mu=wq["mu"], dt=inputs.riemann_dt(states, dx, gamma=wq["gamma"]), dx=dx,
+                      bc=(1, 1), max_steps=32, model="ddf", gamma=wq["gamma"], prandtl=wq["prandtl"],
+                      layout=LAYOUT, device=dev)
+    lat.init(r, u, v, T)
+    warm_up(torch, lambda: lat.step(1))
+    k = 8
+    t = median_time(torch, ev, RUNS, lambda: lat.step(k)) / k
+    res["ddf_f64_2048"] = {"MLUPS": round(n * n / t / 1e6, 1), "us_per_step": round(t * 1e6, 1),
+                           "bytes_per_lup": 841, "GBps_model": round(841 * n * n / t / 1e9, 1)}
+    del lat
+    torch.cuda.empty_cache()
     return res
 
 

@@ -278,3 +278,28 @@ def test_d2q9_store_hint_bit_identical(dtype, vec, layout):
     _same(a.sensors, b.sensors, "sensors")
     _same(a.flags, b.flags, "flags")
     _same(a.sums, b.sums, "sums")
+
+
+@pytest.mark.parametrize("model,ext", [("bgk", None), ("bgk", ["kn", "qf"]), ("ddf", None),
+                                       ("ddf", ["comp", "sigma_h"])])
+def test_d2q25_store_hint_bit_identical(model, ext):
+    # the D2Q25 kernels take the non-temporal hint on grids of whole tiles
+    # (FP32): forced on and off on a small grid, the same bytes
+    n, steps = 64, 6
+    rho, ux, uy, T, states = inputs.riemann_quadrants(n, seed=4)
+    dx = 1.0 / n
+    kw = dict(model="ddf", gamma=1.4, prandtl=0.71) if model == "ddf" else {}
+    thr = np.array([[1e-7, 1e-6], [1e-4, 1e-3], [1e-3, 1e-2], [1e-3, 1e-2]])
+    out = []
+    for nt in (1, 2):
+        lat = lks.Lattice(25, n, n, "f32", mu=1e-3, dt=inputs.riemann_dt(states, dx, gamma=1.4), dx=dx,
+                          bc=(1, 1), thr=thr, flag_mask=15, max_steps=steps, ext=ext, launch_nt=nt, **kw)
+        lat.init(rho, ux, uy, T)
+        lat.step(steps)
+        out.append(lat)
+    torch.cuda.synchronize()
+    a, b = out
+    _same(a.state, b.state, "state")
+    _same(a.sensors, b.sensors, "sensors")
+    _same(a.flags, b.flags, "flags")
+    _same(a.sums, b.sums, "sums")

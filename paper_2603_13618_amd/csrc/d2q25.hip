@@ -817,11 +817,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     // (dg0 - (C_v - 1)(m2/2 - rho |u|^2/2)) / C_v, the same value as summing
     // the 25 g^neq_i, without the rounding of the equilibrium terms
     const R gsum = fma(-gfac, fma(R(0.5), m2, -(R(0.5) * rho) * fma(ux, ux, uy * uy)), dg0) * R(1.0 / a.cv);
-    R klf = R(0), klg = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qx = R(0),
-      qy = R(0), qfx = R(0), qfy = R(0), qgx = R(0), qgy = R(0);
-    // positivity (f, f^eq, g, g^eq > 0) and the reach of the KL series, per
-    // population (lane masks)
-    bool nonpos = false, far = false;
+    R klf = R(0), klg = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qfx = R(0), qfy = R(0),
+      qgx = R(0), qgy = R(0);
+    // the reach of the KL series (the largest |x|, |y|) and positivity (the
+    // smallest f^eq, g^eq, and the smallest x, y: x > -1 is f > 0)
+    R xmax = R(0), xlo = R(0), eqmin = R(0);
     R deqv[25];
     d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
         const int i = 5 * ia + ib;
@@ -838,25 +838,24 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const R y = gneq * rcp(geq);
         klf += (fneq * x) * kl_series_short(x);
         klg += (gneq * y) * kl_series_short(y);
-        nonpos = nonpos || !(feq > R(0)) || !(geq > R(0)) || !(x > R(-1)) || !(y > R(-1));
-        far = far || !(fabs(x) <= KlShortCut<R>::v) || !(fabs(y) <= KlShortCut<R>::v);
+        xmax = i == 0 ? fmax(fabs(x), fabs(y)) : fmax(xmax, fmax(fabs(x), fabs(y)));
+        xlo = i == 0 ? fmin(x, y) : fmin(xlo, fmin(x, y));
+        eqmin = i == 0 ? fmin(feq, geq) : fmin(eqmin, fmin(feq, geq));
         neq += fabs(fneq) + fabs(gneq);
-        // explicit multiply-adds: the contraction of the stress sums is fixed,
-        // so S_PI is the same bits with and without the extension sensors
+        // explicit multiply-adds: the contraction of the stress and flux sums
+        // is fixed, so S_PI and S_Q are the same bits with and without the
+        // extension sensors
         pxx = fma(vx * vx, fneq, pxx);
         pxy = fma(vx * vy, fneq, pxy);
         pyy = fma(vy * vy, fneq, pyy);
-        const R e = R(0.5) * (vx * vx + vy * vy);
-        qx += vx * (gneq + e * fneq);
-        qy += vy * (gneq + e * fneq);
-        const R cx = vx - ux, cy = vy - uy;
-        const R hc = R(0.5) * (cx * cx + cy * cy) * fneq;
-        qfx += hc * cx;
-        qfy += hc * cy;
-        qgx += cx * gneq;
-        qgy += cy * gneq;
+        // raw third moments: sum v |v|^2/2 f^neq and sum v g^neq
+        qfx = fma(R(gh5_xi(ia) * 0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))), fneq, qfx);
+        qfy = fma(R(gh5_xi(ib) * 0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))), fneq, qfy);
+        qgx = fma(vx, gneq, qgx);
+        qgy = fma(vy, gneq, qgy);
     });
-    if (far && !nonpos) {
+    const bool nonpos = !(eqmin > R(0)) || !(xlo > R(-1));
+    if (!(xmax <= KlShortCut<R>::v) && !nonpos) {
         // rare: some population far from equilibrium (or NaN): the closed
         // form, one population at a time.  Cells with a positivity fault
         // skip it: their S_KL is +inf whatever the sums (on the paper's
@@ -874,6 +873,18 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
             klg += geq * kl_phi((gc[i] - dgeq) * rcp(geq));
             __builtin_amdgcn_sched_barrier(0);
         });
+    }
+    // the total energy flux q = sum v (g^neq + |v|^2/2 f^neq) (S_Q), and the
+    // heat fluxes relative to u: with sum f^neq = 0 and sum v f^neq = 0,
+    // q_f = 1/2 sum |v - u|^2 (v - u) f^neq = Q_f - P u - (tr P / 2) u, and
+    // q_g = sum (v - u) g^neq = Q_g - u sum g^neq
+    const R qx = qfx + qgx, qy = qfy + qgy;
+    {
+        const R htr = R(0.5) * (pxx + pyy);
+        qfx = qfx - fma(pxx, ux, fma(pxy, uy, htr * ux));
+        qfy = qfy - fma(pxy, ux, fma(pyy, uy, htr * uy));
+        qgx = fma(-ux, gsum, qgx);
+        qgy = fma(-uy, gsum, qgy);
     }
 
     // q^neq through an opaque copy in both instantiations: the extension's use
@@ -1009,8 +1020,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     }
 
     // sum f ln(f/f^eq) = sum f^eq phi(x) (f and f^eq carry the same mass);
-    // sum g ln(g/g^eq) = sum g^eq phi(y) + sum g^neq
-    const R klsum = fabs(klf) + fabs(klg + gsum);
+    // sum g ln(g/g^eq) = sum g^eq phi(y) + sum g^neq.  sum g^neq through an
+    // opaque copy: it also feeds q_g, and whether the compiler fuses its
+    // product into this sum must not depend on the extension sensors
+    const R klsum = fabs(klf) + fabs(klg + pin(gsum));
     const bool fault = nonpos || !(klsum == klsum);
     const R s_kl = fault ? R(INFINITY) : klsum;
     // explicit multiply-adds: the same bits with and without the extension

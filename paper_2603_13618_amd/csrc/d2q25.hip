@@ -51,13 +51,16 @@
 // minimum waves per SIMD the f kernel's register allocation must allow (0 =
 // compiler's choice).  Left alone the compiler gives the f kernel a budget
 // of one wave per SIMD; two waves fit without spilling (three spill).
-// Narrow tiles let more workgroups share a CU across the barriers and 16 x 8
-// stages the fewest halo cells per cell of the shapes that fit.
+// Rows of 32 cells are whole 128-byte lines (whole-line reads, and stores
+// that may carry the non-temporal hint); four rows keep the workgroup small
+// enough for several to share a CU across the barriers.  Step at 2048^2
+// (both kernels): 32 x 4 660 us, 32 x 2 685, 32 x 8 683, 64 x 2 690, 64 x 4
+// 676, 128 x 2 740, 16 x 8 706, 16 x 16 761; 32 x 4 without the hint 678.
 #ifndef LKS_DDF_TX
-#define LKS_DDF_TX 16
+#define LKS_DDF_TX 32
 #endif
 #ifndef LKS_DDF_TY
-#define LKS_DDF_TY 8
+#define LKS_DDF_TY 4
 #endif
 #ifndef LKS_DDF_WAVES
 #define LKS_DDF_WAVES 2
@@ -820,8 +823,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     R klf = R(0), klg = R(0), neq = R(0), pxx = R(0), pxy = R(0), pyy = R(0), qfx = R(0), qfy = R(0),
       qgx = R(0), qgy = R(0);
     // the reach of the KL series (the largest |x|, |y|) and positivity (the
-    // smallest f^eq, g^eq, and the smallest x, y: x > -1 is f > 0)
+    // smallest f^eq, and the smallest x, y: x > -1 is f > 0).  g^eq = (C_v - 1)
+    // T f^eq, so g^eq > 0 wherever f^eq > 0 and T > 0, and 1/g^eq is 1/f^eq
+    // times igT = 1/((C_v - 1) T)
     R xmax = R(0), xlo = R(0), eqmin = R(0);
+    const R igT = rcp(gfac * Tc);
     R deqv[25];
     d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
         const int i = 5 * ia + ib;
@@ -830,17 +836,17 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         deqv[i] = deq;
         const R fneq = fc[i] - deq;
         const R feq = w * rho0 + deq;
-        const R x = fneq * rcp(feq);
+        const R rf = rcp(feq);
+        const R x = fneq * rf;
         // deviation of g^eq from (C_v - 1) w rho0: (C_v - 1)(T deq + (T - 1) w rho0)
         const R dgeq = gfac * (Tc * deq + tm1 * (w * rho0));
         const R gneq = gc[i] - dgeq;
-        const R geq = gfac * (w * rho0) + dgeq;
-        const R y = gneq * rcp(geq);
+        const R y = gneq * (rf * igT);
         klf += (fneq * x) * kl_series_short(x);
         klg += (gneq * y) * kl_series_short(y);
         xmax = i == 0 ? fmax(fabs(x), fabs(y)) : fmax(xmax, fmax(fabs(x), fabs(y)));
         xlo = i == 0 ? fmin(x, y) : fmin(xlo, fmin(x, y));
-        eqmin = i == 0 ? fmin(feq, geq) : fmin(eqmin, fmin(feq, geq));
+        eqmin = i == 0 ? feq : fmin(eqmin, feq);
         neq += fabs(fneq) + fabs(gneq);
         // explicit multiply-adds: the contraction of the stress and flux sums
         // is fixed, so S_PI and S_Q are the same bits with and without the
@@ -854,7 +860,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         qgx = fma(vx, gneq, qgx);
         qgy = fma(vy, gneq, qgy);
     });
-    const bool nonpos = !(eqmin > R(0)) || !(xlo > R(-1));
+    const bool nonpos = !(eqmin > R(0)) || !(Tc > R(0)) || !(xlo > R(-1));
     if (!(xmax <= KlShortCut<R>::v) && !nonpos) {
         // rare: some population far from equilibrium (or NaN): the closed
         // form, one population at a time.  Cells with a positivity fault

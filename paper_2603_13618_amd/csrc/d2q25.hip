@@ -274,6 +274,15 @@ template <typename R> struct AdvScale {
     __device__ __forceinline__ R neg(int i) const { return i == 3 ? -s3 : i == 4 ? -s4 : i == 1 ? s3 : s4; }
 };
 
+// q . v of population (ia, ib), without the terms of a zero component
+template <typename R>
+__device__ __forceinline__ R q_dot_v(R qx, R qy, int ia, int ib)
+{
+    if (ia == 2) return qy * R(gh5_xi(ib));
+    if (ib == 2) return qx * R(gh5_xi(ia));
+    return fma(qx, R(gh5_xi(ia)), qy * R(gh5_xi(ib)));
+}
+
 // o - (dt/dx) (xi_ia dF_x + xi_ib dF_y): the flux divergence of population
 // (ia, ib), value d, whose staged plane is t, added to o
 template <typename R>
@@ -850,15 +859,19 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         neq += fabs(fneq) + fabs(gneq);
         // explicit multiply-adds: the contraction of the stress and flux sums
         // is fixed, so S_PI and S_Q are the same bits with and without the
-        // extension sensors
-        pxx = fma(vx * vx, fneq, pxx);
-        pxy = fma(vx * vy, fneq, pxy);
-        pyy = fma(vy * vy, fneq, pyy);
+        // extension sensors; terms of a zero velocity component are skipped
+        if (ia != 2) pxx = fma(vx * vx, fneq, pxx);
+        if (ia != 2 && ib != 2) pxy = fma(vx * vy, fneq, pxy);
+        if (ib != 2) pyy = fma(vy * vy, fneq, pyy);
         // raw third moments: sum v |v|^2/2 f^neq and sum v g^neq
-        qfx = fma(R(gh5_xi(ia) * 0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))), fneq, qfx);
-        qfy = fma(R(gh5_xi(ib) * 0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))), fneq, qfy);
-        qgx = fma(vx, gneq, qgx);
-        qgy = fma(vy, gneq, qgy);
+        if (ia != 2) {
+            qfx = fma(R(gh5_xi(ia) * 0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))), fneq, qfx);
+            qgx = fma(vx, gneq, qgx);
+        }
+        if (ib != 2) {
+            qfy = fma(R(gh5_xi(ib) * 0.5 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib))), fneq, qfy);
+            qgy = fma(vy, gneq, qgy);
+        }
     });
     const bool nonpos = !(eqmin > R(0)) || !(Tc > R(0)) || !(xlo > R(-1));
     if (!(xmax <= KlShortCut<R>::v) && !nonpos) {
@@ -994,27 +1007,35 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     const long long off = (long long)Y * nx + X;
     const long long poff = a.L.at(0, Y, X);
     __syncthreads();              // the staged f of the whole tile (pass 1 read registers only)
-    R qe = R(0);
-    sfor25<25>([&](auto ic) {
+    auto update = [&](auto ic, R dfs, bool has_dfs) {
         constexpr int i = decltype(ic)::value;
-        constexpr int ia = i / 5, ib = i % 5;
-        const R w = R(gh5_w(ia) * gh5_w(ib));
-        const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
         const R d = fc[i];
-        const R fneq = d - deqv[i];
-        // f* - f^eq = w (q_f . v)(|v|^2/4 - 1)
-        const R dfs = w * (qfx * vx + qfy * vy) * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
-        qe += fabs(dfs);
-        const R o = advect<R>(fma(B12, dfs, fma(-B1, fneq, d)), adv, lds + i * T::kPlane, rb, tx, d, ia, ib);
+        const R c = fma(-B1, d - deqv[i], d);
+        const R o = advect<R>(has_dfs ? fma(B12, dfs, c) : c, adv, lds + i * T::kPlane, rb, tx, d, i / 5, i % 5);
         if (active) put_pop<NTS>(fout + i * a.L.pp + poff, Store<S>::from_real(o));
-    });
-    // g* - g^eq = w (q_g . v): its part of the QE sensor; g itself is updated
-    // by d2q25_ddf_g_kernel from the cell state handed over here
-    sfor25<25>([&](auto ic) {
+    };
+    // f* - f^eq = w (q_f . v)(|v|^2/4 - 1) is odd in v: population 24 - i
+    // (velocity -v_i) takes -dfs_i bit for bit, and the rest population
+    // none.  S_QE sums |f* - f^eq| and |g* - g^eq| = |w (q_g . v)| over the
+    // populations: twice the sums over one of each pair
+    R qe = R(0);
+    update(std::integral_constant<int, 12>{}, R(0), false);
+    sfor25<12>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ia = i / 5, ib = i % 5;
-        qe += fabs(R(gh5_w(ia) * gh5_w(ib)) * (qgx * R(gh5_xi(ia)) + qgy * R(gh5_xi(ib))));
+        const R dfs = R(gh5_w(ia) * gh5_w(ib) * (0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0)) *
+                      q_dot_v(qfx, qfy, ia, ib);
+        qe += fabs(dfs);
+        update(ic, dfs, true);
+        update(std::integral_constant<int, 24 - i>{}, -dfs, true);
     });
+    // g itself is updated by d2q25_ddf_g_kernel from the cell state handed
+    // over here
+    sfor25<12>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        qe += fabs(R(gh5_w(i / 5) * gh5_w(i % 5)) * q_dot_v(qgx, qgy, i / 5, i % 5));
+    });
+    qe = R(2) * qe;
     if (active) {
         R* aux = static_cast<R*>(a.aux) + off;
         aux[0] = drho;

@@ -41,7 +41,7 @@ FUSED_KERNEL_PREFIX = "d2q9_fused_lds"     # rocprofv3 prints the bare name
 # sensors + 1 flag per cell (the method's bytes; the two kernels of the step
 # also hand 6 values per cell over and read g's own cell twice: 569 B)
 BYTES_F32_DDF = 421
-DDF_KERNEL = "d2q25_ddf_kernel<float,32,4,false,false,true> + d2q25_ddf_g_kernel<float,32,8,false,true>"
+DDF_KERNEL = "d2q25_ddf_kernel<float,32,4,false,false,true> + d2q25_ddf_g_kernel<float,64,4,false,true>"
 # the single-distribution D2Q25 step (FP32): 25 x 4 read + 25 x 4 written + 4 x 4
 # sensors + 1 flag per cell
 BYTES_F32_Q25 = 217

@@ -65,16 +65,17 @@
 #ifndef LKS_DDF_WAVES
 #define LKS_DDF_WAVES 2
 #endif
-// FP32 tile of the double distribution's g kernel (its own launch grid): as
-// for the single distribution, rows of 32 cells stage whole 128-byte lines;
-// and the waves per SIMD its register allocation must allow (0 = the
-// compiler's choice, four; five fit without spilling but measured 752 against
-// 745 us for the step at 2048^2)
+// FP32 tile of the double distribution's g kernel (its own launch grid):
+// rows of 64 cells, two whole 128-byte lines, stage fewer halo columns per
+// cell than rows of 32; and the waves per SIMD its register allocation must
+// allow (0 = the compiler's choice, four).  Step at 2048^2 (both kernels, the
+// f kernel on 32 x 4): g on 64 x 4 637 us, 128 x 4 638, 128 x 2 641, 64 x 8
+// 648, 32 x 8 653 (five waves 657), 32 x 4 662, 32 x 16 663, 64 x 2 668.
 #ifndef LKS_DDF_G_TX
-#define LKS_DDF_G_TX 32
+#define LKS_DDF_G_TX 64
 #endif
 #ifndef LKS_DDF_G_TY
-#define LKS_DDF_G_TY 8
+#define LKS_DDF_G_TY 4
 #endif
 #ifndef LKS_DDF_G_WAVES
 #define LKS_DDF_G_WAVES 0

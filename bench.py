@@ -45,7 +45,7 @@ DDF_KERNEL = "d2q25_ddf_kernel<float,32,4,false,false,true> + d2q25_ddf_g_kernel
 # the single-distribution D2Q25 step (FP32): 25 x 4 read + 25 x 4 written + 4 x 4
 # sensors + 1 flag per cell
 BYTES_F32_Q25 = 217
-Q25_KERNEL = "d2q25_kernel<float,32,8,false,false>"
+Q25_KERNEL = "d2q25_kernel<float,32,4,false,false,true>"
 LAYOUT = "rows"                 # population layout of every lattice (--layout)
 
 

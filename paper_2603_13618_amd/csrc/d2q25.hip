@@ -34,15 +34,17 @@
 
 // FP32 workgroup tile (cells) of the single-distribution kernel and the
 // minimum waves per SIMD its register allocation must allow (0 = compiler).
-// Measured at 2048^2 (us per step): 32 x 8 290.0, 32 x 4 289.7, 64 x 4 293.2,
-// 64 x 2 300.5, 16 x 8 324.9, 64 x 8 327.6, 32 x 16 339.2; rows of 16 cells
-// are half a 128-byte line, and the staging of 16-wide tiles alone takes as
-// long as the whole step of 32-wide ones.
+// Measured at 2048^2 (us per step, the current kernel with the non-temporal
+// stores): 32 x 4 265.3, 64 x 4 265.2, 32 x 8 268.7, 64 x 2 271.4, 128 x 2
+// 289.8; on an earlier build 16 x 8 324.9, 64 x 8 327.6, 32 x 16 339.2 against
+// 290.0 for 32 x 8: rows of 16 cells are half a 128-byte line, and the
+// staging of 16-wide tiles alone takes as long as the whole step of 32-wide
+// ones.
 #ifndef LKS_Q25_TX
 #define LKS_Q25_TX 32
 #endif
 #ifndef LKS_Q25_TY
-#define LKS_Q25_TY 8
+#define LKS_Q25_TY 4
 #endif
 #ifndef LKS_Q25_WAVES
 #define LKS_Q25_WAVES 0

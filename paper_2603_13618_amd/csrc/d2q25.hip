@@ -142,9 +142,15 @@ __device__ __forceinline__ void hermite_h(R u, R tm1, R (&h)[5])
 
 // f^eq_i - w_i rho0 for all 25 populations from (rho - rho0, rho, u, theta - 1),
 // with the leading "1" of the expansion taken out so nothing cancels:
-// f^eq_ab = w_a w_b rho (1 + Px~_a + sum_nx Px_a[nx] Sy~_b[4 - nx]).
-// Deq25 holds the per-cell factors; group<A>() gives the five populations of
-// x-node A, d2q25_deq all 25.
+// f^eq_ab = w_a w_b rho (1 + s_ab), s_ab = Px~_a + Sy~_b[4] + sum_{n=1..3}
+// Px_a[n] Sy~_b[4 - n] with Px_a[n] = h_n(u_x) He_n(xi_a)/n! and Px~_a their
+// sum over n = 1..4.  Deq25 holds the per-cell factors; group<A>() gives
+// the five populations of x-node A, d2q25_deq all 25.  The nodes are
+// symmetric, xi_{4-a} = -xi_a, so He_n(xi_{4-a}) = (-1)^n He_n(xi_a): with E
+// the even and O the odd powers of the x expansion, s_ab = E + O and
+// s_{4-a,b} = E - O, which pair<A>() uses for x-nodes A and 4 - A together
+// (d2q25_deq_pairs); Sy~_2 has no odd terms (Sy~_2[1] = 0, Sy~_2[3] =
+// Sy~_2[2]).
 template <typename R> struct Deq25 {
     R hx[5];
     R sy[5][5];           // Sy~_b[m] = sum_{n=1..m} hy[n] He_n(xi_b)/n!
@@ -158,7 +164,8 @@ template <typename R> struct Deq25 {
         for (int b = 0; b < 5; ++b) {
             sy[b][0] = R(0);
 #pragma unroll
-            for (int m = 1; m < 5; ++m) sy[b][m] = sy[b][m - 1] + hy[m] * R(gh5_he(b, m));
+            for (int m = 1; m < 5; ++m)
+                sy[b][m] = (b == 2 && m % 2 == 1) ? sy[b][m - 1] : fma(hy[m], R(gh5_he(b, m)), sy[b][m - 1]);
         }
     }
     // the population loops are unrolled by templates: a pragma gives up when
@@ -182,13 +189,48 @@ template <typename R> struct Deq25 {
             use(A, b, R(gh5_w(A) * gh5_w(b)) * (rho * s + drho));
         });
     }
+    // x-nodes A and 4 - A (A < 2), population (A, b) before (4 - A, b); the
+    // same values as group<A>() and group<4 - A>() up to rounding, in fewer
+    // operations
+    template <int A, typename F> __device__ __forceinline__ void pair(F&& use) const
+    {
+        static_assert(A < 2, "pair of x-nodes A and 4 - A");
+        R p[5];
+#pragma unroll
+        for (int n = 1; n < 5; ++n) p[n] = hx[n] * R(gh5_he(A, n));
+        const R pe = p[2] + p[4], po = p[1] + p[3];
+        sfor25<5>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            const R e = fma(p[2], sy[b][2], pe + sy[b][4]);
+            R o;
+            if constexpr (b == 2) o = fma(p[1], sy[b][2], po);
+            else o = fma(p[1], sy[b][3], fma(p[3], sy[b][1], po));
+            const R w = R(gh5_w(A) * gh5_w(b));             // w_{4-A} = w_A
+            use(A, b, w * fma(rho, e + o, drho));
+            use(4 - A, b, w * fma(rho, e - o, drho));
+        });
+    }
 };
 
+// all 25 populations in order
 template <typename R, typename F>
 __device__ __forceinline__ void d2q25_deq(R drho, R rho, R ux, R uy, R tm1, F&& use)
 {
     const Deq25<R> e(drho, rho, ux, uy, tm1);
     sfor25<5>([&](auto ac) { e.template group<decltype(ac)::value>(use); });
+}
+
+// all 25 populations by mirror pairs of x-nodes: 0 and 4, 1 and 3, then 2
+// (population 0 first).  Fewer operations than d2q25_deq, but a caller
+// holding many registers across it may need more (the single-distribution
+// kernel's rare fallback then cost it a wave per SIMD)
+template <typename R, typename F>
+__device__ __forceinline__ void d2q25_deq_pairs(R drho, R rho, R ux, R uy, R tm1, F&& use)
+{
+    const Deq25<R> e(drho, rho, ux, uy, tm1);
+    e.template pair<0>(use);
+    e.template pair<1>(use);
+    e.template group<2>(use);
 }
 
 // class of |v|^2 of population (a, b) on GH5 x GH5: 0 centre, 1 one inner
@@ -841,7 +883,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
     R xmax = R(0), xlo = R(0), eqmin = R(0);
     const R igT = rcp(gfac * Tc);
     R deqv[25];
-    d2q25_deq<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
+    d2q25_deq_pairs<R>(drho, rho, ux, uy, tm1, [&](int ia, int ib, R deq) {
         const int i = 5 * ia + ib;
         const R w = R(gh5_w(ia) * gh5_w(ib));
         const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
@@ -927,7 +969,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const bool needV = a.x.mask & 0x4u, needW = a.x.mask & 0x8u;
         ExtAcc<R> ef, eg;
         R vfx = R(0), vfy = R(0), wfx = R(0), wfy = R(0), vgx = R(0), vgy = R(0), wgx = R(0), wgy = R(0);
-        d2q25_deq<R>(drho_p, rho_p, ux_p, uy_p, tm1_p, [&](int ia, int ib, R deq) {
+        d2q25_deq_pairs<R>(drho_p, rho_p, ux_p, uy_p, tm1_p, [&](int ia, int ib, R deq) {
             const int i = 5 * ia + ib;
             const R w = R(gh5_w(ia) * gh5_w(ib));
             const R iw = R(1.0 / (gh5_w(ia) * gh5_w(ib)));

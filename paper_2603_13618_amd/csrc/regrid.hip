@@ -26,11 +26,15 @@ namespace lks {
 namespace {
 
 constexpr int kTX = 256;               // output cells per workgroup tile, x (64 words)
-constexpr int kTY = 16;                // and y
+#ifndef LKS_BUF_TY
+#define LKS_BUF_TY 16
+#endif
+constexpr int kTY = LKS_BUF_TY;        // and y
 constexpr int kMaxB = kMaxBuffer;
 constexpr int kWX = kTX / 4;           // output words per tile row
-constexpr int kPadW = 2;               // halo words on each side (b <= 8 cells)
-constexpr int kSW = kWX + 2 * kPadW;   // staged words per row
+constexpr int kPadW = 4;               // halo words on each side: 16 bytes, so interior rows
+                                       // load as whole 16-byte pieces (b <= 8 cells needs 2)
+constexpr int kSW = kWX + 2 * kPadW;   // staged words per row (18 pieces of 16 bytes)
 
 __device__ __forceinline__ int wrap_or_clamp(int j, int n, int bc)
 {
@@ -61,70 +65,132 @@ __device__ __forceinline__ uint32_t bytes_at(uint32_t lo, uint32_t hi, int r)
 
 // One workgroup: a kTX x kTY output tile.  Stage the tile's codes with a
 // b-row and kPadW-word halo in LDS, OR along x over 2b + 1 cells (byte
-// shifts of neighbouring words), then along y over 2b + 1 rows.
+// shifts of neighbouring words), then along y over 2b + 1 rows.  Each thread
+// takes four words (16 cells) at a time through the LDS phases; rows of a
+// multiple of 16 cells on 16-byte aligned buffers move 16 bytes per lane in
+// and out of HBM.
 template <int B>
 __global__ __launch_bounds__(kBlock) void buffer_kernel(const uint8_t* __restrict__ flags,
                                                         uint8_t* __restrict__ out, int nx, int ny,
-                                                        int bc_x, int bc_y, int tiles_x, int aligned4)
+                                                        int bc_x, int bc_y, int tiles_x, int aligned4,
+                                                        int aligned16)
 {
     constexpr int b = B;
-    __shared__ uint32_t src[kTY + 2 * kMaxB][kSW];
-    __shared__ uint32_t rowor[kTY + 2 * kMaxB][kWX];
+    __shared__ __attribute__((aligned(16))) uint32_t src[kTY + 2 * kMaxB][kSW];
+    __shared__ __attribute__((aligned(16))) uint32_t rowor[kTY + 2 * kMaxB][kWX];
     const int X0 = (blockIdx.x % tiles_x) * kTX;
     const int Y0 = (blockIdx.x / tiles_x) * kTY;
     const int H = kTY + 2 * b;
-    // interior tiles of rows whose length is a multiple of 4 load whole words
-    const bool words = aligned4 && (nx % 4 == 0) && X0 >= 4 * kPadW && X0 + kTX + 4 * kPadW <= nx;
-
-    for (int e = threadIdx.x; e < H * kSW; e += kBlock) {
-        const int r = e / kSW, w = e % kSW;
-        const int gy = wrap_or_clamp(Y0 + r - b, ny, bc_y);
-        const uint8_t* row = flags + (long long)gy * nx;
-        uint32_t v;
-        if (words) {
-            v = *reinterpret_cast<const uint32_t*>(row + X0 + 4 * (w - kPadW));
-        } else {
-            v = 0;
+    // Rows of a multiple of 16 cells on 16-byte aligned buffers load whole
+    // 16-byte pieces, the ghost pieces too: a piece starts at a multiple of
+    // 16, so off the grid it is a whole piece one period away (periodic) or
+    // 16 copies of the edge cell (outflow).  Each thread issues all of its
+    // loads before it waits for any.  Otherwise interior tiles of rows whose
+    // length is a multiple of 4 load whole words, the rest single cells.
+    const bool words = aligned4 && X0 >= 4 * kPadW && X0 + kTX + 4 * kPadW <= nx;
+    if (aligned16) {
+        constexpr int kP = kSW / 4;                                         // pieces per staged row
+        constexpr int kItems = ((kTY + 2 * kMaxB) * kP + kBlock - 1) / kBlock;
+        uint4 v[kItems];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int gx = wrap_or_clamp(X0 + 4 * (w - kPadW) + k, nx, bc_x);
-                v |= (uint32_t)row[gx] << (8 * k);
+        for (int k = 0; k < kItems; ++k) {
+            const int e = threadIdx.x + k * kBlock;
+            v[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < H * kP) {
+                const int r = e / kP, q = e % kP;
+                const uint8_t* row = flags + (long long)wrap_or_clamp(Y0 + r - b, ny, bc_y) * nx;
+                const int gx = X0 + 16 * q - 4 * kPadW;
+                if (gx >= 0 && gx < nx) {
+                    v[k] = *reinterpret_cast<const uint4*>(row + gx);
+                } else if (bc_x == 0) {
+                    v[k] = *reinterpret_cast<const uint4*>(row + wrap_or_clamp(gx, nx, 0));
+                } else {
+                    const uint32_t c = (uint32_t)row[gx < 0 ? 0 : nx - 1] * 0x01010101u;
+                    v[k] = make_uint4(c, c, c, c);
+                }
             }
         }
-        src[r][w] = to_code(v);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < H * kWX; e += kBlock) {
-        const int r = e / kWX, w = e % kWX;
-        const uint32_t a0 = src[r][w], a1 = src[r][w + 1], a2 = src[r][w + 2], a3 = src[r][w + 3],
-                       a4 = src[r][w + 4];
-        // cells 4w .. 4w+3 of the tile sit in word w + kPadW = a2; a cell
-        // shift s in [-b, b] reads bytes from 4 (w + kPadW) + s on
-        const uint32_t win[5] = {a0, a1, a2, a3, a4};
-        uint32_t m = 0;
 #pragma unroll
-        for (int sh = -b; sh <= b; ++sh) {
-            const int p = 4 * kPadW + sh;              // byte offset in the window, 0 .. 16
-            const int q = p >> 2, rr = p & 3;
-            const uint32_t lo = win[q], hi = q < 4 ? win[q + 1] : 0u;
-            m |= bytes_at(lo, hi, rr);
+        for (int k = 0; k < kItems; ++k) {
+            const int e = threadIdx.x + k * kBlock;
+            if (e < H * kP) {
+                const int r = e / kP, q = e % kP;
+                *reinterpret_cast<uint4*>(&src[r][4 * q]) =
+                    make_uint4(to_code(v[k].x), to_code(v[k].y), to_code(v[k].z), to_code(v[k].w));
+            }
         }
-        rowor[r][w] = m;
+    } else {
+        for (int e = threadIdx.x; e < H * kSW; e += kBlock) {
+            const int r = e / kSW, w = e % kSW;
+            const int gy = wrap_or_clamp(Y0 + r - b, ny, bc_y);
+            const uint8_t* row = flags + (long long)gy * nx;
+            uint32_t v;
+            if (words) {
+                v = *reinterpret_cast<const uint32_t*>(row + X0 + 4 * (w - kPadW));
+            } else {
+                v = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int gx = wrap_or_clamp(X0 + 4 * (w - kPadW) + k, nx, bc_x);
+                    v |= (uint32_t)row[gx] << (8 * k);
+                }
+            }
+            src[r][w] = to_code(v);
+        }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTY * kWX; e += kBlock) {
-        const int r = e / kWX, w = e % kWX;
-        const int y = Y0 + r, x = X0 + 4 * w;
-        if (y >= ny || x >= nx) continue;
-        uint32_t m = 0;
+    // words 4c .. 4c + 3 of a row: cell 4w + j of the tile sits in staged word
+    // w + kPadW, and its x window (shifts -b .. b, |shift| <= 8 cells) lies in
+    // staged words w + kPadW - 2 .. w + kPadW + 2, so the four outputs read
+    // staged words 4c + 2 .. 4c + 9, inside the three pieces 4c .. 4c + 11
+    for (int e = threadIdx.x; e < H * (kWX / 4); e += kBlock) {
+        const int r = e / (kWX / 4), c = e % (kWX / 4);
+        const uint4 p0 = *reinterpret_cast<const uint4*>(&src[r][4 * c]);
+        const uint4 p1 = *reinterpret_cast<const uint4*>(&src[r][4 * c + 4]);
+        const uint4 p2 = *reinterpret_cast<const uint4*>(&src[r][4 * c + 8]);
+        const uint32_t win[12] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, p2.y, p2.z, p2.w};
+        uint32_t m[4];
 #pragma unroll
-        for (int k = 0; k <= 2 * b; ++k) m |= rowor[r + k][w];
-        const uint32_t lv = to_level(m);
+        for (int j = 0; j < 4; ++j) {
+            m[j] = 0;
+#pragma unroll
+            for (int sh = -b; sh <= b; ++sh) {
+                const int p = 4 * (j + kPadW) + sh;    // byte offset of the shifted word in the pieces
+                const int q = p >> 2, rr = p & 3;
+                m[j] |= bytes_at(win[q], win[q + 1], rr);
+            }
+        }
+        *reinterpret_cast<uint4*>(&rowor[r][4 * c]) = make_uint4(m[0], m[1], m[2], m[3]);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTY * (kWX / 4); e += kBlock) {
+        const int r = e / (kWX / 4), c = e % (kWX / 4);
+        const int y = Y0 + r, x = X0 + 16 * c;
+        if (y >= ny || x >= nx) continue;
+        uint4 m = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int k = 0; k <= 2 * b; ++k) {
+            const uint4 v = *reinterpret_cast<const uint4*>(&rowor[r + k][4 * c]);
+            m.x |= v.x;
+            m.y |= v.y;
+            m.z |= v.z;
+            m.w |= v.w;
+        }
+        const uint32_t lv[4] = {to_level(m.x), to_level(m.y), to_level(m.z), to_level(m.w)};
         uint8_t* dst = out + (long long)y * nx + x;
-        if (aligned4 && x + 4 <= nx && nx % 4 == 0) {
-            *reinterpret_cast<uint32_t*>(dst) = lv;
+        if (aligned16 && x + 16 <= nx) {
+            *reinterpret_cast<uint4*>(dst) = make_uint4(lv[0], lv[1], lv[2], lv[3]);
         } else {
-            for (int k = 0; k < 4 && x + k < nx; ++k) dst[k] = (uint8_t)(lv >> (8 * k));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xj = x + 4 * j;
+                if (xj >= nx) break;
+                if (aligned4 && xj + 4 <= nx) {
+                    *reinterpret_cast<uint32_t*>(dst + 4 * j) = lv[j];
+                } else {
+                    for (int k = 0; k < 4 && xj + k < nx; ++k) dst[4 * j + k] = (uint8_t)(lv[j] >> (8 * k));
+                }
+            }
         }
     }
 }
@@ -190,11 +256,17 @@ hipError_t launch_tag_buffer(const uint8_t* flags, uint8_t* out, int nx, int ny,
 {
     if (b < 0 || b > kMaxB) return hipErrorInvalidValue;
     const int tiles_x = (nx + kTX - 1) / kTX, tiles_y = (ny + kTY - 1) / kTY;
-    const int aligned4 = ((uintptr_t)flags % 4 == 0) && ((uintptr_t)out % 4 == 0);
+    // whole words need rows of a multiple of 4 bytes on 4-byte aligned
+    // buffers, whole 16-byte pieces rows of a multiple of 16 on 16-byte
+    // aligned ones
+    const int aligned4 = ((uintptr_t)flags % 4 == 0) && ((uintptr_t)out % 4 == 0) && nx % 4 == 0;
+    const int aligned16 = ((uintptr_t)flags % 16 == 0) && ((uintptr_t)out % 16 == 0) && nx % 16 == 0;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block(kBlock);
     switch (b) {
 #define LKS_BUFFER_CASE(B)                                                                          \
-    case B: buffer_kernel<B><<<grid, block, 0, s>>>(flags, out, nx, ny, bc_x, bc_y, tiles_x, aligned4); break;
+    case B:                                                                                         \
+        buffer_kernel<B><<<grid, block, 0, s>>>(flags, out, nx, ny, bc_x, bc_y, tiles_x, aligned4, aligned16); \
+        break;
         LKS_BUFFER_CASE(0) LKS_BUFFER_CASE(1) LKS_BUFFER_CASE(2) LKS_BUFFER_CASE(3) LKS_BUFFER_CASE(4)
         LKS_BUFFER_CASE(5) LKS_BUFFER_CASE(6) LKS_BUFFER_CASE(7) LKS_BUFFER_CASE(8)
 #undef LKS_BUFFER_CASE

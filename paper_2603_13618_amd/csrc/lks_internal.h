@@ -134,7 +134,8 @@ hipError_t launch_d2q25_ddf_moments(int dtype, long long n, const PopLayout& L, 
 
 // Reduce partials[step][nblocks][8] of nsteps steps into sums rows
 // (row0 + step) mod max_rows; adds the reference mass/energy n_cells*rho0*(1, e_ref).
-hipError_t launch_finalize(const double* partials, int nblocks, int nsteps, double* sums,
+// The partials are scratch: chunk sums are written over them.
+hipError_t launch_finalize(double* partials, int nblocks, int nsteps, double* sums,
                            long long row0, int max_rows, double mass_ref, double energy_ref,
                            hipStream_t s);
 

@@ -328,6 +328,46 @@ __device__ __forceinline__ R q_dot_v(R qx, R qy, int ia, int ib)
     return fma(qx, R(gh5_xi(ia)), qy * R(gh5_xi(ib)));
 }
 
+// One population's extension sums: ExtAcc::add, and the entropy-flux sums
+// of the dissipations, V += c v ln(h/w) and W += c v ln(h/h^eq) with ln(h/w)
+// = ln(h^eq/w) + ln(1 + x).  lt is ln(h^eq/w): taken here from t = h^eq/w - 1
+// unless lt_given, and returned.  Each logarithm is taken once, inside the
+// branch of the mask bits that need it (V needs both sums of the kind of L
+// and S, W those of S).
+template <typename R>
+__device__ __forceinline__ void ext_add_vw(ExtAcc<R>& e, const ExtNeed& need, bool needV, bool needW, R fneq_,
+                                           R x_, R f_, R t_, bool lt_given, R& lt, R cvx, R cvy, R& vx, R& vy,
+                                           R& wx, R& wy)
+{
+    const R fneq = pin(fneq_), x = pin(x_), f = pin(f_);
+    e.kn += fabs(x);
+    if (need.L) {
+        if (!lt_given) lt = ln1p_fast(pin(t_));
+        e.L += fneq * lt;
+    }
+    if (need.S) {
+        const R lx = ln1p_fast(x);
+        e.shkl += fneq * lx;
+        if (needV) {
+            const R l = lt + lx;
+            vx += cvx * l;
+            vy += cvy * l;
+        }
+        if (needW) {
+            wx += cvx * lx;
+            wy += cvy * lx;
+        }
+    }
+    if (need.A) {
+        const R y = fneq * rcp(f);             // f^neq / f
+        const R t1 = fneq * y, t2 = t1 * y, t3 = t2 * y;
+        e.a1 += t1;
+        e.a2 += t2;
+        e.a3 += t3;
+        e.a4 += t3 * y;
+    }
+}
+
 // o - (dt/dx) (xi_ia dF_x + xi_ib dF_y): the flux divergence of population
 // (ia, ib), value d, whose staged plane is t, added to o
 template <typename R>
@@ -969,6 +1009,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
         const bool needV = a.x.mask & 0x4u, needW = a.x.mask & 0x8u;
         ExtAcc<R> ef, eg;
         R vfx = R(0), vfy = R(0), wfx = R(0), wfy = R(0), vgx = R(0), vgy = R(0), wgx = R(0), wgy = R(0);
+        // ln(g^eq/w) = ln((C_v - 1) T) + ln(f^eq/w) (g^eq = (C_v - 1) T f^eq)
+        const R lgT = need.L ? ln1p_fast(gfac_p * Tc_p - R(1)) : R(0);
         d2q25_deq_pairs<R>(drho_p, rho_p, ux_p, uy_p, tm1_p, [&](int ia, int ib, R deq) {
             const int i = 5 * ia + ib;
             const R w = R(gh5_w(ia) * gh5_w(ib));
@@ -976,29 +1018,17 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(DdfWave
             const R vx = R(gh5_xi(ia)), vy = R(gh5_xi(ib));
             const R d = pin(fc[i]), dg = pin(gc[i]);
             const R feq = w * rho0_p + deq, fneq = d - deq, x = fneq * rcp(feq);
-            const R tf = (rho0_p - R(1)) + deq * iw;                    // f^eq/w - 1
-            ef.add(need, fneq, x, w * rho0_p + d, tf);
+            // c v of the entropy-flux sums: w (|v|^2/4 - 1) v for f, w v for g
+            const double cf = gh5_w(ia) * gh5_w(ib) * (0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
+            const double cg = gh5_w(ia) * gh5_w(ib);
+            R ltf = R(0);                                                 // ln(f^eq/w)
+            ext_add_vw(ef, need, needV, needW, fneq, x, w * rho0_p + d, (rho0_p - R(1)) + deq * iw, false, ltf,
+                       R(cf * gh5_xi(ia)), R(cf * gh5_xi(ib)), vfx, vfy, wfx, wfy);
             const R dgeq = gfac_p * (Tc_p * deq + tm1_p * (w * rho0_p));
             const R geq = gfac_p * (w * rho0_p) + dgeq, gneq = dg - dgeq, y = gneq * rcp(geq);
-            const R tg = (gfac_p * rho0_p - R(1)) + dgeq * iw;           // g^eq/w - 1
-            eg.add(need, gneq, y, gfac_p * (w * rho0_p) + dg, tg);
-            if (needV || needW) {
-                const R cf = w * R(0.25 * (gh5_xi(ia) * gh5_xi(ia) + gh5_xi(ib) * gh5_xi(ib)) - 1.0);
-                const R lxf = ln1p_fast(x), lxg = ln1p_fast(y);
-                if (needV) {                                   // ln(h/w) = ln(h^eq/w) + ln(1 + x)
-                    const R lf = ln1p_fast(tf) + lxf, lg = ln1p_fast(tg) + lxg;
-                    vfx += cf * vx * lf;
-                    vfy += cf * vy * lf;
-                    vgx += w * vx * lg;
-                    vgy += w * vy * lg;
-                }
-                if (needW) {                                   // ln(h/h^eq) = ln(1 + x)
-                    wfx += cf * vx * lxf;
-                    wfy += cf * vy * lxf;
-                    wgx += w * vx * lxg;
-                    wgy += w * vy * lxg;
-                }
-            }
+            R ltg = ltf + lgT;                                            // ln(g^eq/w)
+            ext_add_vw(eg, need, needV, needW, gneq, y, gfac_p * (w * rho0_p) + dg, R(0), true, ltg,
+                       R(cg * gh5_xi(ia)), R(cg * gh5_xi(ib)), vgx, vgy, wgx, wgy);
         });
         const R inf = R(INFINITY);
         const bool fault_p = nonpos || !(fabs(klf) + fabs(klg + gsum) == fabs(klf) + fabs(klg + gsum));

@@ -46,8 +46,11 @@ def _moment_errs(orc, lat, ref):
     return e_rho, e_u, e_T
 
 
+# (256 x 128 and 192 x 100: 512 and 300 workgroups of 32 x 2 cells, so the
+# partial sums are reduced in two passes, whole chunks and a partial one)
 @pytest.mark.parametrize("nx,ny,bc", [(96, 80, (1, 1)), (40, 36, (0, 0)), (67, 9, (1, 0)),
-                                      (5, 3, (0, 1)), (1, 1, (1, 1))])
+                                      (5, 3, (0, 1)), (1, 1, (1, 1)), (256, 128, (1, 1)),
+                                      (192, 100, (0, 0))])
 def test_fp64_matches_oracle(orc, nx, ny, bc):
     fields, dx, dt = _riemann(nx, ny)
     steps = 12

@@ -72,7 +72,8 @@
 // cell than rows of 32; and the waves per SIMD its register allocation must
 // allow (0 = the compiler's choice, four).  Step at 2048^2 (both kernels, the
 // f kernel on 32 x 4): g on 64 x 4 637 us, 128 x 4 638, 128 x 2 641, 64 x 8
-// 648, 32 x 8 653 (five waves 657), 32 x 4 662, 32 x 16 663, 64 x 2 668.
+// 648, 32 x 8 653 (five waves 657), 32 x 4 662, 32 x 16 663, 64 x 2 668;
+// five waves on 64 x 4 (89 registers) 641 against 634 on one box.
 #ifndef LKS_DDF_G_TX
 #define LKS_DDF_G_TX 64
 #endif

@@ -400,7 +400,12 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     const int nx = a.nx, ny = a.ny;
     const long long plane = a.plane;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
+    // 16-bit storage (VALU-bound): the wave index taken wave-uniform, so the
+    // staging area's LDS addresses are scalar, and row accesses as a uniform
+    // row base plus a 32-bit lane offset (BF16 at 8192^2 649 -> 639 us; the
+    // same forms made FP32 3 % slower, which keeps the plain ones)
+    constexpr bool kHalf = sizeof(raw) == 2;
+    const int wave = kHalf ? __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) : threadIdx.x / kWave;
     const int tx = blockIdx.x % a.g.tiles_x;
     const int rg = blockIdx.x / a.g.tiles_x;
     const int x0 = (tx * kBlock + threadIdx.x) * VEC;
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
             if (active) {
 #pragma unroll
                 for (int p = 0; p < G::NP; ++p) {
-                    gvoid* g = (gvoid*)(row + x0 + p * G::PE);
+                    gvoid* g = kHalf ? (gvoid*)(row + (unsigned)(x0 + p * G::PE)) : (gvoid*)(row + x0 + p * G::PE);
                     lvoid* l = (lvoid*)&stage[wave][i][p * kWave * G::PS];
                     if constexpr (G::PS == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
                     else __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
@@ -470,13 +475,24 @@ __global__ __launch_bounds__(kBlock) LKS_CELL_KERNEL_ATTR void d2q9_fused_lds(
     auto store_row = [&](int y) {
         if (active) {
             const long long off = (long long)y * nx + x0;
-            const long long poff = a.L.at(0, y, x0);
+            if constexpr (kHalf) {
+                const unsigned ux = (unsigned)x0;
+                const long long srow = (long long)y * nx, prow = a.L.at(0, y, 0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) store_vec<S, VEC, NT>(fout + i * a.L.pp + poff, res[i]);
-            store_pack<R, VEC, NT>(sens + off, s_kl);
-            store_pack<R, VEC, NT>(sens + plane + off, s_neq);
-            store_pack<R, VEC, NT>(sens + 2 * plane + off, s_pi);
-            store_pack<uint8_t, VEC, NT>(flags + off, fl);
+                for (int i = 0; i < 9; ++i) store_vec<S, VEC, NT>(fout + (i * a.L.pp + prow) + ux, res[i]);
+                store_pack<R, VEC, NT>(sens + srow + ux, s_kl);
+                store_pack<R, VEC, NT>(sens + (plane + srow) + ux, s_neq);
+                store_pack<R, VEC, NT>(sens + (2 * plane + srow) + ux, s_pi);
+                store_pack<uint8_t, VEC, NT>(flags + srow + ux, fl);
+            } else {
+                const long long poff = a.L.at(0, y, x0);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) store_vec<S, VEC, NT>(fout + i * a.L.pp + poff, res[i]);
+                store_pack<R, VEC, NT>(sens + off, s_kl);
+                store_pack<R, VEC, NT>(sens + plane + off, s_neq);
+                store_pack<R, VEC, NT>(sens + 2 * plane + off, s_pi);
+                store_pack<uint8_t, VEC, NT>(flags + off, fl);
+            }
             if constexpr (EXT) {
 #pragma unroll
                 for (int q = 0; q < kNumExt; ++q)
